@@ -1,0 +1,455 @@
+"""Seeded synthetic scenes for the free-surface lattice Boltzmann step.
+
+This module produces *inputs only*: cell types, fill levels, densities,
+velocities, bubble IDs and the bubble list of a scene.  It contains none of
+the method's arithmetic (no equilibria, no streaming, no curvature, no
+labelling); both the CPU oracle and the GPU library derive everything else
+themselves from these arrays.
+
+Layout: every per-cell array is flat, cell index ``i = x + nx*(y + ny*z)``;
+the velocity is SoA ``u[c*N + i]`` with c = 0, 1, 2 for x, y, z.
+
+Cell types (Sec. 2.2, Fig. 1 of the paper, plus two boundary kinds used by
+the pore set-up of Sec. 3.2): gas G = 0, interface I = 1, liquid L = 2,
+no-slip wall W = 3, gas inlet IN = 4.
+
+Fill levels come from counting sub-cell midpoints that lie in the liquid
+(``ss``**3 midpoints per cell, ``ss`` a power of two), so the initial
+fill levels are exact binary fractions and identical for every consumer.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GAS, IFACE, LIQ, WALL, INLET = 0, 1, 2, 3, 4
+BUBBLE_INLET = 1  # bubble flag bit: the bubble owns inlet cells
+
+P0 = 1.0 / 3.0  # reference pressure rho0 * cs^2 with rho0 = 1 (Sec. 2.2)
+
+
+@dataclass
+class Scene:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    periodic: tuple
+    tau: float
+    sigma: float
+    g: tuple
+    eps: float
+    inject_rate: float
+    cell_type: np.ndarray  # u8 [N]
+    phi: np.ndarray  # f64 [N]
+    rho: np.ndarray  # f64 [N]
+    u: np.ndarray  # f64 [3N]
+    bubble_id: np.ndarray  # i32 [N]
+    bubbles: list  # [(id, flags, v_star, p_init)]; v_star <= 0: derive from p_init
+    steps: int = 0  # horizon the scene is meant for
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def params(self, precision: int = 0, collision: int = 0, **over) -> dict:
+        d = dict(
+            nx=self.nx, ny=self.ny, nz=self.nz, periodic=tuple(self.periodic),
+            precision=precision, collision=collision, tau=self.tau,
+            trt_lambda=3.0 / 16.0, sigma=self.sigma, g=tuple(self.g), p0=P0,
+            eps_convert=self.eps, inject_rate=self.inject_rate,
+            max_bubbles=1024, force_topology=0, freeze_conversions=0,
+        )
+        d.update(over)
+        return d
+
+
+# ---------------------------------------------------------------- helpers
+
+def _grid(nx, ny, nz):
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return x.ravel(), y.ravel(), z.ravel()
+
+
+def _min_image(d, L, periodic):
+    if periodic:
+        return d - L * np.round(d / L)
+    return d
+
+
+def _subsample_fraction(cx, cy, cz, gas_fn, ss):
+    """Fraction of the ss^3 sub-cell midpoints of cells (cx,cy,cz) for which
+    gas_fn(x, y, z) is true.  Evaluated in chunks to bound memory."""
+    off = (np.arange(ss) + 0.5) / ss
+    ox, oy, oz = np.meshgrid(off, off, off, indexing="ij")
+    ox, oy, oz = ox.ravel(), oy.ravel(), oz.ravel()
+    out = np.empty(len(cx), dtype=np.float64)
+    chunk = max(1, (1 << 22) // (ss ** 3))
+    for s in range(0, len(cx), chunk):
+        e = min(len(cx), s + chunk)
+        px = cx[s:e, None] + ox[None, :]
+        py = cy[s:e, None] + oy[None, :]
+        pz = cz[s:e, None] + oz[None, :]
+        out[s:e] = gas_fn(px, py, pz).sum(axis=1) / float(ss ** 3)
+    return out
+
+
+def _gas_fraction(nx, ny, nz, gas_fn, band_fn, ss):
+    """Gas volume fraction per cell.  band_fn(xc, yc, zc) returns
+    (-1: certainly liquid, +1: certainly gas, 0: needs sub-sampling) using
+    cell centres."""
+    x, y, z = _grid(nx, ny, nz)
+    band = band_fn(x + 0.5, y + 0.5, z + 0.5)
+    frac = np.where(band > 0, 1.0, 0.0)
+    cand = np.nonzero(band == 0)[0]
+    if len(cand):
+        frac[cand] = _subsample_fraction(x[cand].astype(np.float64), y[cand].astype(np.float64),
+                                         z[cand].astype(np.float64), gas_fn, ss)
+    return frac
+
+
+def _neighbours18(nx, ny, nz, periodic):
+    """Yield (dx, dy, dz) of the 18 D3Q19 neighbours."""
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                k = abs(dx) + abs(dy) + abs(dz)
+                if 1 <= k <= 2:
+                    yield dx, dy, dz
+
+
+def _shift(a3, dx, dy, dz, periodic, fill):
+    """b[z,y,x] = a[z+dz, y+dy, x+dx] with wrap on periodic axes and `fill`
+    outside the box on the others."""
+    b = a3
+    for axis, d, per in ((2, dx, periodic[0]), (1, dy, periodic[1]), (0, dz, periodic[2])):
+        if d == 0:
+            continue
+        b = np.roll(b, -d, axis=axis)
+        if not per:
+            sl = [slice(None)] * 3
+            sl[axis] = slice(-1, None) if d > 0 else slice(0, 1)
+            b = b.copy()
+            b[tuple(sl)] = fill
+    return b
+
+
+def _any_neighbour(mask3, periodic):
+    out = np.zeros_like(mask3)
+    for dx, dy, dz in _neighbours18(*mask3.shape[::-1], periodic):
+        out |= _shift(mask3, dx, dy, dz, periodic, False)
+    return out
+
+
+def _finish(name, nx, ny, nz, periodic, phi, fixed_type, rho, tau, sigma, g, eps,
+            inject_rate, id_fn, p_init_of, steps, noise=0.0, seed=0, meta=None):
+    """Types from fill levels, closed-layer fix-up, noise and IDs.
+
+    fixed_type: u8 array with 255 where the type follows from phi, or a
+    fixed type (WALL / INLET)."""
+    t = np.where(phi >= 1.0, LIQ, np.where(phi <= 0.0, GAS, IFACE)).astype(np.uint8)
+    t = np.where(fixed_type != 255, fixed_type, t).astype(np.uint8)
+    t3 = t.reshape(nz, ny, nx)
+    # Closed interface layer (Sec. 2.2): no liquid cell may touch gas/inlet.
+    gasish = (t3 == GAS) | (t3 == INLET)
+    bad = (t3 == LIQ) & _any_neighbour(gasish, periodic)
+    t3[bad] = IFACE
+    t = t3.ravel()
+    phi = np.where(t == LIQ, 1.0, np.where((t == GAS) | (t == INLET) | (t == WALL), 0.0, phi))
+    if noise > 0.0:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        r = rng.uniform(-noise, noise, size=len(phi))
+        phi = np.where(t == IFACE, np.clip(phi + r, 0.0, 1.0), phi)
+    bid = np.full(len(t), -1, dtype=np.int32)
+    setc = (t == GAS) | (t == IFACE) | (t == INLET)
+    x, y, z = _grid(nx, ny, nz)
+    bid[setc] = id_fn(x[setc] + 0.5, y[setc] + 0.5, z[setc] + 0.5).astype(np.int32)
+    ids = sorted(set(int(v) for v in np.unique(bid[setc])))
+    bubbles = []
+    for b in ids:
+        flags = BUBBLE_INLET if np.any((bid == b) & (t == INLET)) else 0
+        bubbles.append((b, flags, -1.0, float(p_init_of(b))))
+    u = np.zeros(3 * len(t), dtype=np.float64)
+    return Scene(name, nx, ny, nz, tuple(int(p) for p in periodic), tau, sigma, tuple(g), eps,
+                 inject_rate, t.astype(np.uint8), phi.astype(np.float64), rho.astype(np.float64),
+                 u, bid, bubbles, steps, meta or {})
+
+
+# ---------------------------------------------------------------- scenes
+
+def spheres(n=(32, 32, 32), centers=((16.0, 16.0, 16.0),), radii=(8.0,), periodic=(1, 1, 1),
+            tau=0.6, sigma=1e-3, g=(0.0, 0.0, 0.0), eps=1e-2, p_init=None, rho_l=None,
+            walls=False, ss=16, noise=0.0, seed=0, steps=200, name="spheres",
+            velocity=None):
+    """Gas spheres in liquid.  Each sphere is its own bubble (ID = its index).
+
+    rho_l: liquid density; default is Laplace equilibrium with the first
+    sphere at bubble pressure p0: rho_l = 1 - 6 sigma / R.
+    p_init: per-bubble initial pressure (default p0 for every bubble).
+    walls: no-slip wall layer on every face (periodic must then be 0).
+    velocity: optional callable (x, y, z) -> (ux, uy, uz) at cell centres.
+    """
+    nx, ny, nz = n
+    per = tuple(int(p) for p in periodic)
+    cs = np.asarray(centers, dtype=np.float64)
+    rs = np.asarray(radii, dtype=np.float64)
+
+    def dist2(px, py, pz, k):
+        dx = _min_image(px - cs[k, 0], nx, per[0])
+        dy = _min_image(py - cs[k, 1], ny, per[1])
+        dz = _min_image(pz - cs[k, 2], nz, per[2])
+        return dx * dx + dy * dy + dz * dz
+
+    def gas_fn(px, py, pz):
+        m = np.zeros(px.shape, dtype=bool)
+        for k in range(len(rs)):
+            m |= dist2(px, py, pz, k) < rs[k] ** 2
+        return m
+
+    h = math.sqrt(3.0) / 2.0 + 1e-9
+
+    def band_fn(xc, yc, zc):
+        out = np.full(xc.shape, -1, dtype=np.int8)
+        for k in range(len(rs)):
+            d = np.sqrt(dist2(xc, yc, zc, k))
+            out = np.where(d + h < rs[k], 1, out)
+            out = np.where((np.abs(d - rs[k]) <= h) & (out != 1), 0, out)
+        return out
+
+    gas = _gas_fraction(nx, ny, nz, gas_fn, band_fn, ss)
+    phi = 1.0 - gas
+    fixed = np.full(nx * ny * nz, 255, dtype=np.uint8)
+    x, y, z = _grid(nx, ny, nz)
+    if walls:
+        face = (x == 0) | (x == nx - 1) | (y == 0) | (y == ny - 1) | (z == 0) | (z == nz - 1)
+        fixed[face] = WALL
+    if rho_l is None:
+        rho_l = 1.0 - 6.0 * sigma / float(rs[0])
+    rho = np.full(nx * ny * nz, rho_l, dtype=np.float64)
+    if g[2] != 0.0:
+        rho = rho_l * (1.0 - 3.0 * g[2] * ((nz - 1) / 2.0 - z))
+
+    def id_fn(px, py, pz):
+        best = np.zeros(px.shape, dtype=np.int64)
+        bd = np.full(px.shape, np.inf)
+        for k in range(len(rs)):
+            d = np.sqrt(dist2(px, py, pz, k)) - rs[k]
+            best = np.where(d < bd, k, best)
+            bd = np.minimum(bd, d)
+        return best
+
+    pin = [P0] * len(rs) if p_init is None else list(p_init)
+    sc = _finish(name, nx, ny, nz, per, phi, fixed, rho, tau, sigma, g, eps, 0.0, id_fn,
+                 lambda b: pin[b], steps, noise, seed,
+                 meta=dict(centers=cs.tolist(), radii=rs.tolist()))
+    if velocity is not None:
+        ux, uy, uz = velocity(x + 0.5, y + 0.5, z + 0.5)
+        fluid = (sc.cell_type == IFACE) | (sc.cell_type == LIQ)
+        sc.u[: sc.n] = np.where(fluid, ux, 0.0)
+        sc.u[sc.n: 2 * sc.n] = np.where(fluid, uy, 0.0)
+        sc.u[2 * sc.n:] = np.where(fluid, uz, 0.0)
+    return sc
+
+
+def threads(n=(64, 64, 256), axes=((32.0, 32.0),), R=8.0, amp=0.1, wavelength=72.0,
+            periodic=(1, 1, 1), tau=0.55, sigma=5e-3, noise=1e-3, seed=1604, ss=8,
+            steps=20000, name="threads", phase=0.0):
+    """Gas threads along z with radius R(1 + amp sin(2 pi z / wavelength)),
+    evaluated per sub-sample z.  Each thread is one bubble."""
+    nx, ny, nz = n
+    per = tuple(int(p) for p in periodic)
+    ax = np.asarray(axes, dtype=np.float64)
+
+    def radius(pz):
+        return R * (1.0 + amp * np.sin(2.0 * np.pi * pz / wavelength + phase))
+
+    def r2(px, py, k):
+        dx = _min_image(px - ax[k, 0], nx, per[0])
+        dy = _min_image(py - ax[k, 1], ny, per[1])
+        return dx * dx + dy * dy
+
+    def gas_fn(px, py, pz):
+        m = np.zeros(px.shape, dtype=bool)
+        rr = radius(pz) ** 2
+        for k in range(len(ax)):
+            m |= r2(px, py, k) < rr
+        return m
+
+    rmin, rmax = R * (1.0 - amp), R * (1.0 + amp)
+    h = math.sqrt(3.0) / 2.0 + 1e-9
+
+    def band_fn(xc, yc, zc):
+        out = np.full(xc.shape, -1, dtype=np.int8)
+        for k in range(len(ax)):
+            d = np.sqrt(r2(xc, yc, k))
+            out = np.where(d + h < rmin, 1, out)
+            out = np.where((d - h <= rmax) & (d + h >= rmin) & (out != 1), 0, out)
+        return out
+
+    gas = _gas_fraction(nx, ny, nz, gas_fn, band_fn, ss)
+    phi = 1.0 - gas
+    fixed = np.full(nx * ny * nz, 255, dtype=np.uint8)
+    rho = np.full(nx * ny * nz, 1.0 - 3.0 * sigma / R, dtype=np.float64)
+
+    def id_fn(px, py, pz):
+        best = np.zeros(px.shape, dtype=np.int64)
+        bd = np.full(px.shape, np.inf)
+        for k in range(len(ax)):
+            d = r2(px, py, k)
+            best = np.where(d < bd, k, best)
+            bd = np.minimum(bd, d)
+        return best
+
+    return _finish(name, nx, ny, nz, per, phi, fixed, rho, tau, sigma, (0.0, 0.0, 0.0), 1e-2,
+                   0.0, id_fn, lambda b: P0, steps, noise, seed,
+                   meta=dict(axes=ax.tolist(), R=R, amp=amp, wavelength=wavelength))
+
+
+def orifice(n=(128, 128, 256), r=6.0, g=1e-5, tau=0.6, sigma=2e-3, Q=0.05, steps=50000,
+            name="orifice"):
+    """Closed box with wall layers on all faces; the bottom wall is pierced by
+    a disk of inlet cells of radius r; cells at z = 1 above the disk start as
+    half-filled interface cells; everything else is liquid in hydrostatic
+    balance rho(z) = 1 + 3 g (nz/2 - z)."""
+    nx, ny, nz = n
+    x, y, z = _grid(nx, ny, nz)
+    cx, cy = nx / 2.0, ny / 2.0
+    disk = (x + 0.5 - cx) ** 2 + (y + 0.5 - cy) ** 2 <= r * r
+    face = (x == 0) | (x == nx - 1) | (y == 0) | (y == ny - 1) | (z == 0) | (z == nz - 1)
+    fixed = np.full(nx * ny * nz, 255, dtype=np.uint8)
+    fixed[face] = WALL
+    fixed[(z == 0) & disk & ~((x == 0) | (x == nx - 1) | (y == 0) | (y == ny - 1))] = INLET
+    phi = np.ones(nx * ny * nz, dtype=np.float64)
+    phi[(z == 1) & disk] = 0.5
+    rho = 1.0 + 3.0 * g * (nz / 2.0 - z)
+    p_in = float(1.0 + 3.0 * g * (nz / 2.0 - 1)) / 3.0
+    return _finish(name, nx, ny, nz, (0, 0, 0), phi, fixed, rho, tau, sigma, (0.0, 0.0, -g), 1e-2,
+                   Q, lambda px, py, pz: np.zeros(px.shape, dtype=np.int64), lambda b: p_in,
+                   steps, meta=dict(r=r))
+
+
+# ------------------------------------------------------ named configurations
+
+def config(name: str) -> Scene:
+    """The named workloads.
+
+    c1     32^3 periodic, one gas sphere R = 8 at the centre, tau 0.6,
+           sigma 1e-3, 200 steps (static bubble; Laplace jump).
+    c2     64x64x256 periodic, gas thread R = 8 along z, radius perturbation
+           0.1 R with wavelength 9 R, 1e-3 uniform fill-level noise,
+           tau 0.55, sigma 5e-3 (thread rupture, Sec. 3.1 stand-in).
+    c3     128x128x256 walled box, inlet disk r = 6 in the bottom wall,
+           Q = 0.05 per step, g = 1e-5 in -z, tau 0.6, sigma 2e-3
+           (bubble detachment, Sec. 3.2 stand-in).
+    p1     256^3 periodic, 16 gas threads of the c2 geometry on a 4x4 grid
+           (x, y in {32, 96, 160, 224}), seed 256.
+    p0     256^3 all liquid (bulk ceiling).
+    """
+    if name == "c1":
+        return spheres(name="c1")
+    if name == "c2":
+        return threads(name="c2")
+    if name == "c3":
+        return orifice(name="c3")
+    if name == "p1":
+        axes = [(float(a), float(b)) for b in (32, 96, 160, 224) for a in (32, 96, 160, 224)]
+        return threads(n=(256, 256, 256), axes=axes, seed=256, steps=4000, name="p1")
+    if name == "p0":
+        return spheres(n=(256, 256, 256), centers=(), radii=(), name="p0", steps=4000,
+                       rho_l=1.0, tau=0.55)
+    raise KeyError(name)
+
+
+# ------------------------------------------------------------ small scenes
+
+def random_blobs(n=(20, 18, 16), nblob=3, seed=0, periodic=(1, 1, 1), walls=False,
+                 rmin=2.5, rmax=4.5, tau=0.6, sigma=2e-2, g=(0.0, 0.0, 0.0), noise=0.05,
+                 vel=0.05, p_scale=(0.9, 1.2), name="blobs"):
+    """A few random gas spheres (possibly close together), random bubble
+    pressures and a random smooth velocity field; used to drive conversions,
+    merges and splits quickly in small parity cases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = n
+    lo = 2.0 if walls else 0.0
+    cs = np.stack([rng.uniform(lo + rmax, nx - lo - rmax, nblob) if walls else rng.uniform(0, nx, nblob),
+                   rng.uniform(lo + rmax, ny - lo - rmax, nblob) if walls else rng.uniform(0, ny, nblob),
+                   rng.uniform(lo + rmax, nz - lo - rmax, nblob) if walls else rng.uniform(0, nz, nblob)], 1)
+    rs = rng.uniform(rmin, rmax, nblob)
+    pin = list(P0 * rng.uniform(p_scale[0], p_scale[1], nblob))
+    kx, ky, kz = (2 * np.pi / nx, 2 * np.pi / ny, 2 * np.pi / nz)
+    a = rng.uniform(-vel, vel, 6)
+
+    def velocity(px, py, pz):
+        return (a[0] * np.sin(ky * py + a[3]), a[1] * np.sin(kz * pz + a[4]),
+                a[2] * np.sin(kx * px + a[5]))
+
+    sc = spheres(n=n, centers=cs, radii=rs, periodic=(0, 0, 0) if walls else periodic,
+                 tau=tau, sigma=sigma, g=g, walls=walls, p_init=pin, ss=8, noise=noise,
+                 seed=seed + 1, steps=0, name=name, rho_l=1.0, velocity=velocity)
+    return sc
+
+
+def merge_ids_if_touching(sc: Scene) -> Scene:
+    """Give every gas/interface/inlet component one bubble ID (the smallest
+    ID it contains) so that overlapping random spheres form valid scenes.
+    A plain breadth-first search over 18-neighbour adjacency; this is scene
+    preparation, run once, not part of the time step."""
+    nx, ny, nz, per = sc.nx, sc.ny, sc.nz, sc.periodic
+    t = sc.cell_type
+    setc = (t == GAS) | (t == IFACE) | (t == INLET)
+    bid = sc.bubble_id.copy()
+    seen = np.zeros(len(t), dtype=bool)
+    offs = list(_neighbours18(nx, ny, nz, per))
+    for s in np.nonzero(setc)[0]:
+        if seen[s]:
+            continue
+        comp, stack = [], [int(s)]
+        seen[s] = True
+        while stack:
+            c = stack.pop()
+            comp.append(c)
+            x, y, z = c % nx, (c // nx) % ny, c // (nx * ny)
+            for dx, dy, dz in offs:
+                xx, yy, zz = x + dx, y + dy, z + dz
+                if per[0]:
+                    xx %= nx
+                if per[1]:
+                    yy %= ny
+                if per[2]:
+                    zz %= nz
+                if not (0 <= xx < nx and 0 <= yy < ny and 0 <= zz < nz):
+                    continue
+                j = xx + nx * (yy + ny * zz)
+                if setc[j] and not seen[j]:
+                    seen[j] = True
+                    stack.append(j)
+        comp = np.asarray(comp)
+        bid[comp] = bid[comp].min()
+    live = sorted(set(int(v) for v in np.unique(bid[setc])))
+    sc.bubble_id = bid
+    sc.bubbles = [b for b in sc.bubbles if b[0] in live]
+    return sc
+
+
+def layers(spec, ny=4, nz=4, rho=1.0, tau=0.6, sigma=0.0, g=(0.0, 0.0, 0.0), eps=1e-2,
+           p_init=None, velocity=(0.0, 0.0, 0.0), name="layers"):
+    """A periodic box made of x-layers; spec is a list of (type, phi, id)
+    per x index (id -1 for liquid).  Used for hand-built merge / split /
+    flat-interface cases."""
+    nx = len(spec)
+    N = nx * ny * nz
+    x, y, z = _grid(nx, ny, nz)
+    t = np.asarray([s[0] for s in spec], np.uint8)[x]
+    phi = np.asarray([s[1] for s in spec], np.float64)[x]
+    bid = np.asarray([s[2] for s in spec], np.int32)[x]
+    ids = sorted(set(int(s[2]) for s in spec if s[0] in (GAS, IFACE, INLET)))
+    pin = {b: P0 for b in ids} if p_init is None else dict(p_init)
+    fluid = (t == IFACE) | (t == LIQ)
+    u = np.zeros(3 * N)
+    for c in range(3):
+        u[c * N:(c + 1) * N] = np.where(fluid, velocity[c], 0.0)
+    return Scene(name, nx, ny, nz, (1, 1, 1), tau, sigma, tuple(g), eps, 0.0, t, phi,
+                 np.full(N, rho), u, bid, [(b, 0, -1.0, pin[b]) for b in ids])
