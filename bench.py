@@ -1,0 +1,188 @@
+"""Benchmark of the FSLBM step with the enhanced bubble model on one MI355X.
+
+Default workload: 256^3 periodic box with 16 gas threads (radius 8, 0.1 R
+sinusoidal radius perturbation of wavelength 72, 1e-3 fill-level noise),
+tau = 0.55, sigma = 5e-3, FP32 storage and arithmetic.  The warm-up brings
+the threads to the Rayleigh-Plateau breakup, so the timed window contains
+bubble splits (labelling runs).
+
+Prints one JSON line (rank 0, N = 1) with the whole-step throughput in
+MLUPS, the HBM roofline of the dominant kernel (liquid-cell stream-collide)
+measured with HIP events on the library's stream, and the CPU oracle timed
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+METRIC = "FSLBM MLUPS and % of HBM roofline; served p50/p99 latency vs plain"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bulk_bytes_per_launch(counts: dict, store_bytes: int) -> float:
+    """Algorithmic bytes of one launch of the liquid-cell kernel: every
+    liquid cell pulls 19 PDFs and writes 19 PDFs and reads and writes its
+    flag byte; gas, wall and inlet cells copy their flag byte (1 + 1 B);
+    interface cells only have their flag read (1 B)."""
+    return (counts["liq"] * (2 * 19 * store_bytes + 2) + counts["other"] * 2 + counts["iface"] * 1)
+
+
+def count_types(t) -> dict:
+    import numpy as np
+
+    b = np.bincount(t, minlength=5)
+    return dict(gas=int(b[0]), iface=int(b[1]), liq=int(b[2]), other=int(b[0] + b[3] + b[4]))
+
+
+def cpu_baseline(scene, seconds: float, threads: int) -> dict:
+    """The oracle as it stands, on the host cores, on whole steps of the same
+    workload until about `seconds` of CPU time have passed."""
+    import oracle
+
+    oracle.build(force=False)
+    oracle.set_threads(threads)
+    o = oracle.Oracle.from_scene(scene)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 50:
+            break
+    mlups = scene.n * steps / el / 1e6
+    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{scene.name} {scene.nx}x{scene.ny}x{scene.nz}, FP64 oracle, first {steps} "
+                      f"step(s) from the initial state, {el:.1f} s wall"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--warmup", type=int, default=2500)
+    ap.add_argument("--workload", default="p1")
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16dev"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1604_01632_amd as F
+    import scenes
+
+    torch.cuda.set_device(0)
+    sc = scenes.config(args.workload)
+    prec = F.PRECISIONS[args.precision]
+    store_bytes = {0: 8, 1: 4, 2: 2}[prec]
+    dom = F.Domain.from_scene(sc, args.precision)
+    N = sc.n
+    log(f"[bench] {sc.name}: {sc.nx}x{sc.ny}x{sc.nz} ({N} cells) {args.precision}; "
+        f"warmup {args.warmup} steps")
+    dom.step(args.warmup)
+    torch.cuda.synchronize()
+    r0 = dom.read(("cell_type",))
+    c0 = count_types(r0["cell_type"])
+    s0 = r0["scalars"]
+    b0 = dom.bubbles()
+
+    F.fslbm_set_timing(dom.handle, True)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    dom.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    T = F.fslbm_get_timing(dom.handle)
+    F.fslbm_set_timing(dom.handle, False)
+
+    r1 = dom.read(("cell_type",))
+    c1 = count_types(r1["cell_type"])
+    s1 = r1["scalars"]
+    b1 = dom.bubbles()
+    ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
+    mlups = N / (ms_per_step * 1e-3) / 1e6
+    counts = {k: 0.5 * (c0[k] + c1[k]) for k in c0}
+    bytes_bulk = bulk_bytes_per_launch(counts, store_bytes)
+    bulk_avg_ms = T["bulk_ms"] / max(1, T["steps"])
+    achieved = bytes_bulk / (bulk_avg_ms * 1e-3) / 1e9
+    phases = {k: round(T[k] / max(1, T["steps"]) * 1e3, 2) for k in
+              ("bulk_ms", "iface_ms", "convert_ms", "excess_ms", "gather_ms", "label_ms",
+               "bubbles_ms")}
+    log(f"[bench] per-step phase times (us): {phases}")
+    log(f"[bench] window: topology changes {s1['n_topology'] - s0['n_topology']}, bubbles "
+        f"{len(b0['id'])} -> {len(b1['id'])}, mass drift "
+        f"{abs(s1['total_mass'] - s0['total_mass']) / s0['total_mass']:.2e}, cells {c1}")
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16dev": "f16-storage/f32"}[args.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": f"{sc.name}: {sc.nx}x{sc.ny}x{sc.nz} periodic D3Q19 FSLBM + bubble model, "
+                        "16 gas threads R=8 (0.1R sinusoidal perturbation, wavelength 72, 1e-3 "
+                        f"noise), tau={sc.tau}, sigma={sc.sigma}, {args.precision}, timed after "
+                        f"{args.warmup} warm-up steps",
+            "cells": N,
+            "precision": args.precision,
+            "topology_changes_in_window": int(s1["n_topology"] - s0["n_topology"]),
+            "bubbles_start_end": [int(len(b0["id"])), int(len(b1["id"]))],
+            "whole_step_alg_GBs": round(N * (2 * 19 * store_bytes + 8) / (ms_per_step * 1e-3) / 1e9, 1),
+            "phase_us": phases,
+        },
+        "roofline": {
+            "kernel": "k_bulk (liquid-cell stream-collide)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_launch": int(bytes_bulk),
+            "avg_launch_us": round(bulk_avg_ms * 1e3, 2),
+        },
+    }
+    dom.close()
+    del dom
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        log(f"[bench] cpu baseline: oracle on {threads} threads, ~{args.cpu_seconds} s")
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds, threads)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

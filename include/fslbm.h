@@ -1,0 +1,194 @@
+/*
+ * fslbm.h - C ABI of the MI355X free-surface lattice Boltzmann library with
+ * the enhanced bubble model of Anderl, Bogner, Rauh, Ruede, Delgado,
+ * "Free Surface Lattice Boltzmann with Enhanced Bubble Model"
+ * (arXiv:1604.01632).
+ *
+ * One call of fslbm_step advances one domain by whole time steps:
+ *   - D3Q19 stream and BGK (or TRT) collision with a Guo body force
+ *     (Sec. 2.1);
+ *   - interface mass exchange (Sec. 2.2, mass-exchange equation) and fill
+ *     levels phi = m / rho;
+ *   - reconstruction of the PDFs missing on the gas side from the gas
+ *     pressure p_V + 2 sigma kappa (Sec. 2.2, reconstruction and gas-pressure
+ *     equations);
+ *   - interface -> liquid / gas conversion keeping a closed interface layer,
+ *     with excess-mass redistribution (Sec. 2.2);
+ *   - per-bubble volume, ideal-gas pressure p = p0 V* / V (Sec. 2.2,
+ *     ideal-gas equation), and bubble merge (Sec. 2.3.1) and split
+ *     (Sec. 2.3.2) by connected-component labelling of the gas region, run
+ *     only when a conversion can change the topology.
+ *
+ * Conventions
+ *   Cell index i = x + nx * (y + ny * z).  PDFs are SoA: f[a * N + i] with
+ *   the D3Q19 order: 0 rest; 1..6 = +x, -x, +y, -y, +z, -z; 7,8 = (1,1,0),
+ *   (-1,-1,0); 9,10 = (1,-1,0), (-1,1,0); 11,12 = (1,0,1), (-1,0,-1);
+ *   13,14 = (1,0,-1), (-1,0,1); 15,16 = (0,1,1), (0,-1,-1); 17,18 = (0,1,-1),
+ *   (0,-1,1).  Velocities are SoA u[c * N + i].
+ *   Host arrays on this boundary are always FP64, whatever the internal
+ *   precision; the library converts.
+ *   Ownership: the caller owns every host array and the device workspace
+ *   (one allocation of fslbm_workspace_bytes() bytes, e.g. a torch uint8
+ *   tensor).  The library allocates no device memory beyond it and frees
+ *   nothing it did not allocate; a handle owns only host metadata and must
+ *   not outlive its workspace.
+ *   Streams: all device work of a handle is enqueued on the HIP stream given
+ *   at creation; fslbm_step returns after enqueueing.  Reads synchronise that
+ *   stream.  One handle must not be used from two threads at once; distinct
+ *   handles are independent.
+ *   Errors: every call returns FSLBM_OK (0) or a negative status;
+ *   fslbm_last_error() returns the calling thread's message for the last
+ *   failure.  Device-side failures (bubble table full, non-finite mass) are
+ *   reported by the next synchronising call.
+ */
+#ifndef FSLBM_H
+#define FSLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FSLBM_OK = 0,
+  FSLBM_EINVAL = -1,    /* invalid argument or input state */
+  FSLBM_ENOMEM = -2,    /* workspace too small */
+  FSLBM_EDEVICE = -3,   /* HIP runtime error */
+  FSLBM_ENUMERIC = -4,  /* non-finite total mass detected */
+  FSLBM_ECAPACITY = -5  /* bubble table full */
+};
+
+/* Cell types (Sec. 2.2, Fig. 1, plus walls and gas inlets of Sec. 3.2). */
+enum { FSLBM_GAS = 0, FSLBM_INTERFACE = 1, FSLBM_LIQUID = 2, FSLBM_WALL = 3, FSLBM_INLET = 4 };
+
+/* Storage precision of PDFs and fields.  FP64: FP64 arithmetic.  FP32 and
+ * FP16DEV (PDFs stored as FP16 deviations from the lattice weights):
+ * FP32 arithmetic; per-bubble volumes, pressures and the total mass are
+ * always accumulated in FP64. */
+enum { FSLBM_FP64 = 0, FSLBM_FP32 = 1, FSLBM_FP16DEV = 2 };
+
+/* Collision operator: BGK (Sec. 2.1) or two-relaxation-time. */
+enum { FSLBM_BGK = 0, FSLBM_TRT = 1 };
+
+/* Bubble flag bits. */
+enum { FSLBM_BUBBLE_INLET = 1 };
+
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t periodic[3];  /* 1: periodic axis; 0: the two face layers must be
+                           WALL or INLET cells */
+  int32_t precision;    /* FSLBM_FP64 / FSLBM_FP32 / FSLBM_FP16DEV */
+  int32_t collision;    /* FSLBM_BGK / FSLBM_TRT */
+  double tau;           /* relaxation time, omega = 1 / tau; > 1/2 */
+  double trt_lambda;    /* TRT magic parameter (3/16 is typical) */
+  double sigma;         /* surface tension (Laplace pressure 2 sigma kappa) */
+  double g[3];          /* body-force acceleration */
+  double p0;            /* reference pressure rho0 cs^2 = 1/3 */
+  double eps_convert;   /* interface -> liquid when phi > 1 + eps,
+                           interface -> gas when phi < -eps */
+  double inject_rate;   /* V* added per step to each bubble owning INLET cells */
+  int32_t max_bubbles;  /* capacity of the device bubble table (>= 1) */
+  int32_t force_topology; /* 1: label the gas region every step (testing) */
+} fslbm_params;
+
+/* Initial bubble: v_star > 0 gives V* directly (restart); otherwise
+ * V* = V(0) p_init / p0, with V(0) the volume of the initial state. */
+typedef struct {
+  int32_t id;
+  int32_t flags;
+  double v_star;
+  double p_init;
+} fslbm_bubble_init;
+
+typedef struct {
+  int32_t id;
+  int32_t flags;     /* FSLBM_BUBBLE_INLET */
+  double volume;     /* V: gas cells count 1, interface cells 1 - phi */
+  double v_star;     /* V*: gas amount at the reference pressure */
+  double pressure;   /* p0 V* / max(V, 1e-2) */
+  int64_t n_cells;   /* gas + interface + inlet cells carrying this ID */
+} fslbm_bubble;
+
+typedef struct {
+  int64_t step;        /* time steps done */
+  int32_t next_id;     /* next fresh bubble ID */
+  int32_t n_bubbles;   /* live bubbles */
+  double bucket;       /* excess mass without an interface neighbour, spread
+                          over all interface cells in the next step */
+  double total_mass;   /* sum over liquid rho + interface m + bucket, FP64,
+                          of the last step */
+  int64_t n_topology;  /* steps in which labelling ran */
+} fslbm_scalars;
+
+/* Exact device workspace size for these parameters (0 on invalid params). */
+size_t fslbm_workspace_bytes(const fslbm_params *params);
+
+/* Validate and upload an initial state and create a handle.
+ *   cell_type[N] (u8), phi[N] (interface fill levels; ignored elsewhere),
+ *   rho[N] and u[3N] (used to build f = f_eq(rho, u) when f_init is NULL),
+ *   bubble_id[N] (IDs of GAS / INTERFACE / INLET cells; ignored elsewhere),
+ *   bubbles[n_bubbles], f_init[19N] or NULL, mass_init[N] (interface masses
+ *   of a checkpoint; NULL: m = phi rho, Sec. 2.2), restore (step, next_id,
+ *   bucket of a checkpoint) or NULL.  A checkpoint read with
+ *   fslbm_read_fields / fslbm_bubbles and passed back through f_init,
+ *   mass_init, restore and v_star continues bit for bit.
+ *   device_workspace: device pointer to >= fslbm_workspace_bytes() bytes,
+ *   256-byte aligned; stream: hipStream_t (NULL = default stream).
+ * EINVAL if: sizes or tau out of range; a type is unknown; a non-periodic
+ * face layer holds a cell that is not WALL or INLET, or a WALL cell lies
+ * elsewhere; a LIQUID cell touches a GAS or INLET cell (18-neighbourhood);
+ * touching gas-region cells carry different IDs; an ID is not listed; an
+ * interface fill level lies outside [-0.1, 1.1]; rho <= 0 on a fluid cell;
+ * more bubbles than max_bubbles.  ENOMEM if the workspace is too small. */
+int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const double *phi,
+                 const double *rho, const double *u, const int32_t *bubble_id,
+                 const fslbm_bubble_init *bubbles, int32_t n_bubbles, const double *f_init,
+                 const double *mass_init, const fslbm_scalars *restore, void *device_workspace,
+                 size_t workspace_bytes, void *stream, void **out_handle);
+
+/* Enqueue n_steps >= 0 time steps on the handle's stream. */
+int fslbm_step(void *handle, int32_t n_steps);
+
+/* Synchronise and copy state to the host; any pointer may be NULL.
+ * f[19N] is the post-collision PDF set (undefined on GAS / WALL / INLET
+ * cells), mass is m on interface cells and rho on liquid cells, rho and u
+ * are recovered from f (u = sum c f / rho - g / 2). */
+int fslbm_read_fields(void *handle, uint8_t *cell_type, double *phi, double *mass, double *f,
+                      int32_t *bubble_id, double *rho, double *u, fslbm_scalars *scalars);
+
+/* Synchronise and copy the live bubbles, sorted by ID, into out[capacity];
+ * *n_out receives the number of live bubbles (ECAPACITY if > capacity). */
+int fslbm_bubbles(void *handle, fslbm_bubble *out, int32_t capacity, int32_t *n_out);
+
+/* Synchronise and report device-side failures of past steps. */
+int fslbm_sync(void *handle);
+
+/* GPU time per phase of the steps enqueued while timing was enabled,
+ * measured with HIP events on the handle's stream (bulk = liquid-cell
+ * stream-collide kernel, iface = interface kernel, gather includes the
+ * per-bubble volume kernel, label = the labelling kernels, which return at
+ * once unless a topology change is possible). */
+typedef struct {
+  double bulk_ms, iface_ms, convert_ms, excess_ms, gather_ms, label_ms, bubbles_ms;
+  double step_ms;   /* sum of the above */
+  int64_t steps;    /* timed steps */
+} fslbm_timing;
+
+/* Enable (1) or disable (0) event timing; clears the accumulated times. */
+int fslbm_set_timing(void *handle, int32_t enable);
+
+/* Synchronise, report the accumulated times and clear them. */
+int fslbm_get_timing(void *handle, fslbm_timing *out);
+
+/* Destroy the handle (no device memory is freed: it belongs to the caller). */
+int fslbm_destroy(void *handle);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *fslbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

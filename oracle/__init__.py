@@ -72,6 +72,8 @@ def lib():
         L.orc_collide.argtypes = [C.POINTER(_Params), P, P, P, P]
         L.orc_geometry.argtypes = [P, P, P]
         L.orc_label.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P]
+        L.orc_fsum.restype = C.c_double
+        L.orc_fsum.argtypes = [P, C.c_int64]
         L.orc_set_threads.argtypes = [C.c_int32]
         L.orc_threads.restype = C.c_int32
         _lib = L
@@ -125,6 +127,11 @@ def collide(params: dict, fin):
     u = np.zeros(3, np.float64)
     lib().orc_collide(C.byref(p), _ptr(fin), _ptr(fout), _ptr(rho), _ptr(u))
     return fout, float(rho[0]), u
+
+
+def fsum(values) -> float:
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    return float(lib().orc_fsum(_ptr(v), len(v)))
 
 
 def label(inset: np.ndarray, shape, periodic) -> np.ndarray:

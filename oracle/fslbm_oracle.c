@@ -56,9 +56,77 @@ static int opposite(int a) {
   return (a % 2 == 1) ? a + 1 : a - 1;
 }
 
+/* ------------------------------------------------- exactly rounded sums -- */
+
+/* Sums of per-cell quantities (bubble volumes, gas amounts, the orphan
+ * bucket, the total mass) are exactly rounded: the result is the exact sum
+ * of the terms rounded once to the nearest double, independent of order.
+ * Shewchuk's method (1997): keep non-overlapping partials whose sum is
+ * exact, updated with error-free two-sums; at the end add them from the
+ * largest down and correct a half-way case so that ties round to even. */
+typedef struct {
+  double *p;
+  int n, cap;
+} xsum;
+
+static void xsum_add(xsum *a, double x) {
+  int k = 0;
+  for (int j = 0; j < a->n; ++j) {
+    double y = a->p[j];
+    if (fabs(x) < fabs(y)) {
+      double t = x;
+      x = y;
+      y = t;
+    }
+    double hi = x + y;
+    double lo = y - (hi - x);
+    if (lo != 0.0) a->p[k++] = lo;
+    x = hi;
+  }
+  if (k == a->cap) {
+    a->cap = a->cap ? 2 * a->cap : 8;
+    a->p = realloc(a->p, sizeof(double) * a->cap);
+  }
+  a->p[k++] = x;
+  a->n = k;
+}
+
+static double xsum_value(const xsum *a) {
+  int n = a->n;
+  if (n == 0) return 0.0;
+  double hi = a->p[--n], lo = 0.0;
+  while (n > 0) {
+    double x = hi, y = a->p[--n];
+    hi = x + y;
+    lo = y - (hi - x);
+    if (lo != 0.0) break;
+  }
+  /* the partials left below lo push a half-way result up or down */
+  if (n > 0 && ((lo < 0.0 && a->p[n - 1] < 0.0) || (lo > 0.0 && a->p[n - 1] > 0.0))) {
+    double y = lo * 2.0;
+    double x = hi + y;
+    if (y == x - hi) hi = x;
+  }
+  return hi;
+}
+
+static void xsum_free(xsum *a) {
+  free(a->p);
+  a->p = NULL;
+  a->n = a->cap = 0;
+}
+
+double orc_fsum(const double *v, int64_t n) {
+  xsum a = {0};
+  for (int64_t k = 0; k < n; ++k) xsum_add(&a, v[k]);
+  double r = xsum_value(&a);
+  xsum_free(&a);
+  return r;
+}
+
 struct part {
   int32_t bubble; /* index into the old bubble table */
-  double vol;
+  xsum vol;       /* gas volume of the bubble's cells in the component */
   int64_t ncell;
 };
 
@@ -270,7 +338,8 @@ static double height_curvature_axis(const orc *o, const double *phi, const uint8
   double Hbb = H[1][2] - 2.0 * H[1][1] + H[1][0];
   double Hab = 0.25 * (H[2][2] - H[2][0] - H[0][2] + H[0][0]);
   double num = Haa * (1.0 + Hb * Hb) + Hbb * (1.0 + Ha * Ha) - 2.0 * Ha * Hb * Hab;
-  double den = pow(1.0 + Ha * Ha + Hb * Hb, 1.5);
+  double q = 1.0 + Ha * Ha + Hb * Hb;
+  double den = q * sqrt(q);
   return -0.5 * num / den;
 }
 
@@ -393,12 +462,12 @@ static void set_err(char *err, int32_t len, const char *msg) {
 }
 
 static void compute_mass(orc *o) {
-  double M = 0.0;
-  for (int64_t i = 0; i < o->N; ++i) {
-    if (o->type[i] == ORC_L) M += o->m[i];
-    else if (o->type[i] == ORC_I) M += o->m[i];
-  }
-  o->mass = M + o->bucket;
+  xsum M = {0};
+  for (int64_t i = 0; i < o->N; ++i)
+    if (o->type[i] == ORC_L || o->type[i] == ORC_I) xsum_add(&M, o->m[i]);
+  xsum_add(&M, o->bucket);
+  o->mass = xsum_value(&M);
+  xsum_free(&M);
 }
 
 orc *orc_create(const orc_params *p, const uint8_t *type, const double *phi, const double *rho,
@@ -495,16 +564,24 @@ orc *orc_create(const orc_params *p, const uint8_t *type, const double *phi, con
     o->b_ncell[k] = 0;
     if (b_id[k] > maxid) maxid = b_id[k];
   }
+  xsum *vacc = calloc((size_t)(nb > 0 ? nb : 1), sizeof(xsum));
   for (int64_t i = 0; i < N; ++i) {
     if (!in_gas_region(o->type[i])) continue;
     int32_t k = bubble_index(o, o->id[i]);
     if (k < 0) {
       snprintf(msg, sizeof msg, "cell %lld: bubble ID %d not listed", (long long)i, o->id[i]);
+      for (int32_t q = 0; q < nb; ++q) xsum_free(&vacc[q]);
+      free(vacc);
       goto fail;
     }
-    o->b_vol[k] += cell_gas_volume(o->type[i], o->phi[i]);
+    xsum_add(&vacc[k], cell_gas_volume(o->type[i], o->phi[i]));
     o->b_ncell[k] += 1;
   }
+  for (int32_t k = 0; k < nb; ++k) {
+    o->b_vol[k] = xsum_value(&vacc[k]);
+    xsum_free(&vacc[k]);
+  }
+  free(vacc);
   for (int32_t k = 0; k < nb; ++k) {
     o->b_vstar[k] = b_vstar[k] > 0.0 ? b_vstar[k] : o->b_vol[k] * b_pinit[k] / p->p0;
     o->b_p[k] = bubble_pressure(p->p0, o->b_vstar[k], o->b_vol[k]);
@@ -664,27 +741,21 @@ static int any_neighbour_type(const orc *o, int64_t i, uint8_t t) {
 
 struct comp {
   int64_t root;
-  int32_t nparts, cap;
-  struct part *parts;
+  int32_t *ids; /* distinct old bubbles (table indices) in the component */
+  int32_t nids, cap;
+  xsum vol, vstar;
   int inlet;
   int64_t ncell;
 };
 
-static void comp_add(struct comp *c, int32_t bubble, double vol) {
-  for (int32_t k = 0; k < c->nparts; ++k)
-    if (c->parts[k].bubble == bubble) {
-      c->parts[k].vol += vol;
-      c->parts[k].ncell += 1;
-      return;
-    }
-  if (c->nparts == c->cap) {
+static void comp_note(struct comp *c, int32_t b) {
+  for (int32_t k = 0; k < c->nids; ++k)
+    if (c->ids[k] == b) return;
+  if (c->nids == c->cap) {
     c->cap = c->cap ? 2 * c->cap : 4;
-    c->parts = realloc(c->parts, sizeof(struct part) * c->cap);
+    c->ids = realloc(c->ids, sizeof(int32_t) * c->cap);
   }
-  c->parts[c->nparts].bubble = bubble;
-  c->parts[c->nparts].vol = vol;
-  c->parts[c->nparts].ncell = 1;
-  c->nparts += 1;
+  c->ids[c->nids++] = b;
 }
 
 /* Merge (Sec. 2.3.1) and split (Sec. 2.3.2) through one canonical rule on
@@ -692,8 +763,10 @@ static void comp_add(struct comp *c, int32_t bubble, double vol) {
  *  - K keeps the ID b if b is the only bubble in K and K the only
  *    component of b;
  *  - otherwise K becomes a new bubble with a fresh ID (in order of K's
- *    smallest cell index), V = sum over K of the gas volume and
- *    V* = sum_b V*_b V(b in K) / V_b.
+ *    smallest cell index) whose volume is the gas volume of its cells and
+ *    whose gas amount V* is carried by its cells: each cell of an old bubble
+ *    b brings V*_b / V_b times its gas volume (per cell V*_b / n_b if
+ *    V_b <= 0), i.e. V*_K = sum_b V*_b V(b in K) / V_b.
  * For a pure merge this gives V* = sum V*_b and V = sum V_b (Sec. 2.3.1);
  * for a pure split every daughter keeps the mother's pressure (Sec. 2.3.2).
  * Returns 1 if a new ID was created. */
@@ -715,18 +788,25 @@ static int phase_f(orc *o, const double *old_vol, const int64_t *old_ncell) {
       root_to_comp[i] = k;
       ++k;
     }
+  /* gas amount per unit gas volume of every old bubble */
+  double *ratio = calloc((size_t)(o->nb > 0 ? o->nb : 1), sizeof(double));
+  for (int32_t b = 0; b < o->nb; ++b)
+    ratio[b] = old_vol[b] > 0.0 ? o->b_vstar[b] / old_vol[b] : 0.0;
   for (int64_t i = 0; i < N; ++i) {
     if (!inset[i]) continue;
     struct comp *c = &comps[root_to_comp[o->label[i]]];
     int32_t b = bubble_index(o, o->id2[i]);
-    comp_add(c, b, cell_gas_volume(o->type2[i], o->phi2[i]));
+    comp_note(c, b);
+    double w = cell_gas_volume(o->type2[i], o->phi2[i]);
+    xsum_add(&c->vol, w);
+    xsum_add(&c->vstar, old_vol[b] > 0.0 ? ratio[b] * w : o->b_vstar[b] / (double)old_ncell[b]);
     c->ncell += 1;
     if (o->type2[i] == ORC_IN) c->inlet = 1;
   }
   /* number of components each old bubble appears in */
   int32_t *ncomp_of = calloc((size_t)(o->nb > 0 ? o->nb : 1), sizeof(int32_t));
   for (int64_t c = 0; c < ncomp; ++c)
-    for (int32_t q = 0; q < comps[c].nparts; ++q) ncomp_of[comps[c].parts[q].bubble] += 1;
+    for (int32_t q = 0; q < comps[c].nids; ++q) ncomp_of[comps[c].ids[q]] += 1;
   /* new table */
   int32_t nb_new = (int32_t)ncomp;
   int32_t *nid = malloc(sizeof(int32_t) * (nb_new > 0 ? nb_new : 1));
@@ -734,35 +814,26 @@ static int phase_f(orc *o, const double *old_vol, const int64_t *old_ncell) {
   double *nvstar = malloc(sizeof(double) * (nb_new > 0 ? nb_new : 1));
   double *nvol = malloc(sizeof(double) * (nb_new > 0 ? nb_new : 1));
   int64_t *nncell = malloc(sizeof(int64_t) * (nb_new > 0 ? nb_new : 1));
-  int32_t *comp_id = malloc(sizeof(int32_t) * (nb_new > 0 ? nb_new : 1));
   int created = 0;
   for (int64_t c = 0; c < ncomp; ++c) {
     struct comp *K = &comps[c];
-    int keep = (K->nparts == 1) && (ncomp_of[K->parts[0].bubble] == 1);
+    int keep = (K->nids == 1) && (ncomp_of[K->ids[0]] == 1);
     if (keep) {
-      int32_t b = K->parts[0].bubble;
+      int32_t b = K->ids[0];
       nid[c] = o->b_id[b];
       nvstar[c] = o->b_vstar[b];
       nvol[c] = old_vol[b];
     } else {
       nid[c] = o->next_id++;
       created = 1;
-      double vs = 0.0, v = 0.0;
-      for (int32_t q = 0; q < K->nparts; ++q) {
-        int32_t b = K->parts[q].bubble;
-        if (old_vol[b] > 0.0) vs += o->b_vstar[b] * K->parts[q].vol / old_vol[b];
-        else vs += o->b_vstar[b] * (double)K->parts[q].ncell / (double)old_ncell[b];
-        v += K->parts[q].vol;
-      }
-      nvstar[c] = vs;
-      nvol[c] = v;
+      nvstar[c] = xsum_value(&K->vstar);
+      nvol[c] = xsum_value(&K->vol);
     }
     nflags[c] = K->inlet ? 1 : 0;
     nncell[c] = K->ncell;
-    comp_id[c] = nid[c];
   }
   for (int64_t i = 0; i < N; ++i)
-    if (inset[i]) o->id2[i] = comp_id[root_to_comp[o->label[i]]];
+    if (inset[i]) o->id2[i] = nid[root_to_comp[o->label[i]]];
   /* install */
   bubbles_reserve(o, nb_new > 0 ? nb_new : 1);
   o->nb = nb_new;
@@ -773,17 +844,37 @@ static int phase_f(orc *o, const double *old_vol, const int64_t *old_ncell) {
     o->b_vol[c] = nvol[c];
     o->b_ncell[c] = nncell[c];
   }
-  for (int64_t c = 0; c < ncomp; ++c) free(comps[c].parts);
+  for (int64_t c = 0; c < ncomp; ++c) {
+    free(comps[c].ids);
+    xsum_free(&comps[c].vol);
+    xsum_free(&comps[c].vstar);
+  }
   free(comps);
   free(root_to_comp);
+  free(ratio);
   free(ncomp_of);
   free(nid);
   free(nflags);
   free(nvstar);
   free(nvol);
   free(nncell);
-  free(comp_id);
   return created;
+}
+
+/* Density and velocity of a cell recovered from its post-collision PDFs:
+ * rho = sum f*, u = sum c f* / rho - g / 2 (the Guo collision velocity). */
+static void recover_moments(const orc *o, const double *f, int64_t j, double *rho, double *u) {
+  const int64_t N = o->N;
+  double r = 0.0, m[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < Q; ++c) {
+    double v = f[c * N + j];
+    r += v;
+    m[0] += CX[c] * v;
+    m[1] += CY[c] * v;
+    m[2] += CZ[c] * v;
+  }
+  *rho = r;
+  for (int k = 0; k < 3; ++k) u[k] = m[k] / r - 0.5 * o->P.g[k];
 }
 
 /* ---------------------------------------------------------------- step -- */
@@ -840,15 +931,17 @@ static int one_step(orc *o) {
     uint8_t t = o->type[i], t2 = o->type2[i];
     if (t == ORC_G && t2 == ORC_I) {
       /* new interface cell from gas: equilibrium at the mean density and
-       * velocity of the neighbours that were interface or liquid at t;
-       * empty; keeps its bubble ID */
+       * velocity (recovered from the post-collision PDFs) of the neighbours
+       * that were interface or liquid at t; empty; keeps its bubble ID */
       double rs = 0.0, us[3] = {0.0, 0.0, 0.0};
       int cnt = 0;
       for (int a = 1; a < Q; ++a) {
         int64_t j = neighbour(o, i, CX[a], CY[a], CZ[a]);
         if (j < 0 || !(o->type[j] == ORC_I || o->type[j] == ORC_L)) continue;
-        rs += o->rho2[j];
-        for (int k = 0; k < 3; ++k) us[k] += o->u2[k * N + j];
+        double rj, uj[3];
+        recover_moments(o, o->f2, j, &rj, uj);
+        rs += rj;
+        for (int k = 0; k < 3; ++k) us[k] += uj[k];
         ++cnt;
       }
       double rb = rs / cnt, ub[3] = {us[0] / cnt, us[1] / cnt, us[2] / cnt};
@@ -859,9 +952,12 @@ static int one_step(orc *o) {
       for (int k = 0; k < 3; ++k) o->u2[k * N + i] = ub[k];
       o->m2[i] = 0.0;
     } else if (t == ORC_L && t2 == ORC_I) {
-      /* new interface cell from liquid: full, ID of the smallest emptied
-       * neighbour ID */
-      o->m2[i] = o->rho2[i];
+      /* new interface cell from liquid: full (m = rho recovered from its
+       * post-collision PDFs), ID of the smallest emptied neighbour ID */
+      double rr, uu[3];
+      recover_moments(o, o->f2, i, &rr, uu);
+      o->m2[i] = rr;
+      o->rho2[i] = rr;
       int32_t best = -1;
       for (int a = 1; a < Q; ++a) {
         int64_t j = neighbour(o, i, CX[a], CY[a], CZ[a]);
@@ -877,6 +973,8 @@ static int one_step(orc *o) {
    * m - rho; an emptied cell passes on its whole mass.  The excess is split
    * evenly over the neighbours that are interface cells after the
    * conversion; without such a neighbour it goes to the bucket. */
+  xsum bucket = {0};
+  xsum_add(&bucket, o->bucket); /* carried if there was no interface cell */
   for (int64_t i = 0; i < N; ++i) {
     o->excess[i] = 0.0;
     if (!(o->filled[i] || o->emptied[i])) continue;
@@ -894,8 +992,10 @@ static int one_step(orc *o) {
       if (j >= 0 && o->type2[j] == ORC_I) ++nI;
     }
     if (nI > 0) o->excess[i] = e / nI;
-    else o->bucket += e;
+    else xsum_add(&bucket, e);
   }
+  o->bucket = xsum_value(&bucket);
+  xsum_free(&bucket);
   for (int64_t i = 0; i < N; ++i) {
     uint8_t t2 = o->type2[i];
     if (t2 == ORC_I) {
@@ -921,18 +1021,29 @@ static int one_step(orc *o) {
   /* Phase E: volumes of the old bubbles on the new state. */
   double *old_vol = calloc((size_t)(o->nb > 0 ? o->nb : 1), sizeof(double));
   int64_t *old_ncell = calloc((size_t)(o->nb > 0 ? o->nb : 1), sizeof(int64_t));
-  for (int64_t i = 0; i < N; ++i) {
+  xsum *vacc = calloc((size_t)(o->nb > 0 ? o->nb : 1), sizeof(xsum));
+  int bad = 0;
+  for (int64_t i = 0; i < N && !bad; ++i) {
     if (!in_gas_region(o->type2[i])) continue;
     int32_t b = bubble_index(o, o->id2[i]);
     if (b < 0) {
       snprintf(o->err, sizeof o->err, "step %lld: cell %lld has no bubble", (long long)o->step,
                (long long)i);
-      free(old_vol);
-      free(old_ncell);
-      return -1;
+      bad = 1;
+      break;
     }
-    old_vol[b] += cell_gas_volume(o->type2[i], o->phi2[i]);
+    xsum_add(&vacc[b], cell_gas_volume(o->type2[i], o->phi2[i]));
     old_ncell[b] += 1;
+  }
+  for (int32_t b = 0; b < o->nb; ++b) {
+    old_vol[b] = xsum_value(&vacc[b]);
+    xsum_free(&vacc[b]);
+  }
+  free(vacc);
+  if (bad) {
+    free(old_vol);
+    free(old_ncell);
+    return -1;
   }
 
   /* Phase F: topology every step. */

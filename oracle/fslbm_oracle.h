@@ -79,6 +79,9 @@ void orc_collide(const orc_params *p, const double *fin, double *fout, double *r
 /* Normal (Youngs gradient) and curvature (height function) of every
  * interface cell of the current state; other cells get 0. */
 void orc_geometry(const orc *o, double *kappa /*N*/, double *normal /*3N*/);
+/* Exactly rounded sum of n doubles (the exact sum rounded once to the
+ * nearest double, ties to even), as used for all per-cell sums. */
+double orc_fsum(const double *v, int64_t n);
 /* Connected components of the cells with inset[i] != 0 under 18-neighbour
  * adjacency; label = smallest linear index of the component, -1 outside. */
 void orc_label(int32_t nx, int32_t ny, int32_t nz, const int32_t *periodic,

@@ -1,0 +1,640 @@
+// Host implementation of the C ABI declared in include/fslbm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fslbm.h"
+#include "launch.hpp"
+
+using namespace fslbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(FSLBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+constexpr int HOST_CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int HOST_CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int HOST_CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+bool launchers_for(int precision, Launchers &L) {
+  if (precision == FSLBM_FP64) L = launchers_fp64();
+  else if (precision == FSLBM_FP32) L = launchers_fp32();
+  else if (precision == FSLBM_FP16DEV) L = launchers_fp16();
+  else return false;
+  return true;
+}
+
+// ------------------------------------------------------------- layout
+
+enum Arr {
+  A_F0, A_F1, A_FLAG0, A_FLAG1, A_PHI0, A_PHI1, A_MASS, A_RHOI, A_EXCESS, A_BSLOT, A_LAB,
+  A_AUX0, A_AUX1, A_AUX2, A_BID, A_BFLAGS, A_BLIVE, A_BRMIN, A_BRMAX, A_BKEPT, A_NEWROOTS,
+  A_NEWSLOT, A_BVSTAR, A_BVOL, A_BP, A_BRATIO, A_BNGAS, A_BNIFACE, A_BVACC, A_CACC,
+  A_SCALARS, A_MASSACC, A_BUCKETACC, A_NIFACEACC, A_COUNT
+};
+
+struct Layout {
+  size_t off[A_COUNT];
+  size_t total;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Layout make_layout(const fslbm_params &p, const Launchers &L) {
+  const size_t N = (size_t)p.nx * p.ny * p.nz;
+  const size_t B = (size_t)p.max_bubbles;
+  size_t sz[A_COUNT];
+  sz[A_F0] = sz[A_F1] = (size_t)Q * N * L.store_bytes;
+  sz[A_FLAG0] = sz[A_FLAG1] = N;
+  sz[A_PHI0] = sz[A_PHI1] = sz[A_MASS] = sz[A_RHOI] = sz[A_EXCESS] = N * L.real_bytes;
+  sz[A_BSLOT] = sz[A_LAB] = sz[A_AUX0] = sz[A_AUX1] = sz[A_AUX2] = N * 4;
+  sz[A_BID] = sz[A_BFLAGS] = sz[A_BLIVE] = sz[A_BRMIN] = sz[A_BRMAX] = sz[A_BKEPT] =
+      sz[A_NEWROOTS] = sz[A_NEWSLOT] = B * 4;
+  sz[A_BVSTAR] = sz[A_BVOL] = sz[A_BP] = sz[A_BRATIO] = sz[A_BNGAS] = sz[A_BNIFACE] = B * 8;
+  sz[A_BVACC] = B * SUB * VACC * 8;
+  sz[A_CACC] = B * NACC * 8;
+  sz[A_SCALARS] = sizeof(Scalars);
+  sz[A_MASSACC] = SUB_MASS * 2 * 8;
+  sz[A_BUCKETACC] = SUB * EX_WORDS * 8;
+  sz[A_NIFACEACC] = SUB * 8;
+  Layout lay;
+  size_t o = 0;
+  for (int k = 0; k < A_COUNT; ++k) {
+    lay.off[k] = o;
+    o = align256(o + sz[k]);
+  }
+  lay.total = o;
+  return lay;
+}
+
+const char *check_params(const fslbm_params *p) {
+  if (!p) return "params is NULL";
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "sizes must be >= 1";
+  const int n[3] = {p->nx, p->ny, p->nz};
+  for (int k = 0; k < 3; ++k)
+    if (!p->periodic[k] && n[k] < 5) return "a non-periodic axis needs at least 5 cells";
+  if ((long long)p->nx * p->ny * p->nz >= (1ll << 31)) return "more than 2^31 - 1 cells";
+  if (p->ny > 65535 || p->nz > 65535) return "ny and nz must be <= 65535";
+  if (!(p->tau > 0.5)) return "tau must be > 1/2";
+  if (p->collision != FSLBM_BGK && p->collision != FSLBM_TRT) return "unknown collision";
+  if (p->collision == FSLBM_TRT && !(p->trt_lambda > 0.0)) return "trt_lambda must be > 0";
+  if (p->precision < FSLBM_FP64 || p->precision > FSLBM_FP16DEV) return "unknown precision";
+  if (p->max_bubbles < 1 || p->max_bubbles > (1 << 20)) return "max_bubbles out of range";
+  if (!(p->eps_convert >= 0.0)) return "eps_convert must be >= 0";
+  if (!(p->p0 > 0.0)) return "p0 must be > 0";
+  return nullptr;
+}
+
+// --------------------------------------------------------------- context
+
+struct Ctx {
+  // per-phase event timing (fslbm_set_timing)
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // PH_COUNT + 1 per timed step
+  size_t used = 0;
+  fslbm_params P;
+  Launchers L;
+  LaunchCfg cfg;
+  Layout lay;
+  Dev dev[2];  // dev[c]: src buffers = c
+  int cur = 0;
+  long long N = 0;
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+};
+
+template <class T>
+T *at(char *ws, const Layout &lay, Arr a) {
+  return (T *)(ws + lay.off[a]);
+}
+
+void build_devs(Ctx &c) {
+  const Layout &lay = c.lay;
+  char *ws = c.ws;
+  Dev d{};
+  d.nx = c.P.nx;
+  d.ny = c.P.ny;
+  d.nz = c.P.nz;
+  for (int k = 0; k < 3; ++k) d.per[k] = c.P.periodic[k] ? 1 : 0;
+  d.has_walls = !(d.per[0] && d.per[1] && d.per[2]);
+  d.max_bubbles = c.P.max_bubbles;
+  d.force_topology = c.P.force_topology;
+  d.collision = c.P.collision;
+  d.N = c.N;
+  d.omega_p = 1.0 / c.P.tau;
+  d.omega_m = d.omega_p;
+  if (c.P.collision == FSLBM_TRT) d.omega_m = 1.0 / (0.5 + c.P.trt_lambda / (1.0 / d.omega_p - 0.5));
+  d.sigma = c.P.sigma;
+  d.p0 = c.P.p0;
+  d.eps = c.P.eps_convert;
+  d.inject = c.P.inject_rate;
+  for (int k = 0; k < 3; ++k) d.g[k] = c.P.g[k];
+  d.mass = ws + lay.off[A_MASS];
+  d.rhoI = ws + lay.off[A_RHOI];
+  d.excess = ws + lay.off[A_EXCESS];
+  d.bslot = at<int32_t>(ws, lay, A_BSLOT);
+  d.lab = at<int32_t>(ws, lay, A_LAB);
+  d.aux0 = at<int32_t>(ws, lay, A_AUX0);
+  d.aux1 = at<int32_t>(ws, lay, A_AUX1);
+  d.aux2 = at<int32_t>(ws, lay, A_AUX2);
+  d.b_id = at<int32_t>(ws, lay, A_BID);
+  d.b_flags = at<int32_t>(ws, lay, A_BFLAGS);
+  d.b_live = at<int32_t>(ws, lay, A_BLIVE);
+  d.b_rmin = at<int32_t>(ws, lay, A_BRMIN);
+  d.b_rmax = at<int32_t>(ws, lay, A_BRMAX);
+  d.b_kept = at<int32_t>(ws, lay, A_BKEPT);
+  d.newroots = at<int32_t>(ws, lay, A_NEWROOTS);
+  d.newslot = at<int32_t>(ws, lay, A_NEWSLOT);
+  d.b_vstar = at<double>(ws, lay, A_BVSTAR);
+  d.b_vol = at<double>(ws, lay, A_BVOL);
+  d.b_p = at<double>(ws, lay, A_BP);
+  d.b_ratio = at<double>(ws, lay, A_BRATIO);
+  d.b_ngas = at<long long>(ws, lay, A_BNGAS);
+  d.b_niface = at<long long>(ws, lay, A_BNIFACE);
+  d.b_vacc = at<unsigned long long>(ws, lay, A_BVACC);
+  d.c_acc = at<unsigned long long>(ws, lay, A_CACC);
+  d.sc = at<Scalars>(ws, lay, A_SCALARS);
+  d.mass_acc = at<unsigned long long>(ws, lay, A_MASSACC);
+  d.bucket_acc = at<unsigned long long>(ws, lay, A_BUCKETACC);
+  d.niface_acc = at<unsigned long long>(ws, lay, A_NIFACEACC);
+  for (int s = 0; s < 2; ++s) {
+    Dev e = d;
+    e.f_src = ws + lay.off[s == 0 ? A_F0 : A_F1];
+    e.f_dst = ws + lay.off[s == 0 ? A_F1 : A_F0];
+    e.flag_src = at<uint8_t>(ws, lay, s == 0 ? A_FLAG0 : A_FLAG1);
+    e.flag_dst = at<uint8_t>(ws, lay, s == 0 ? A_FLAG1 : A_FLAG0);
+    e.phi_src = ws + lay.off[s == 0 ? A_PHI0 : A_PHI1];
+    e.phi_dst = ws + lay.off[s == 0 ? A_PHI1 : A_PHI0];
+    c.dev[s] = e;
+  }
+}
+
+LaunchCfg make_cfg(const fslbm_params &p) {
+  LaunchCfg cfg;
+  cfg.bx = p.nx >= 256 ? 256 : ((p.nx + 63) / 64) * 64;
+  const long long rows = (long long)p.ny * p.nz;
+  cfg.row_grid = (int)std::min<long long>(rows, 8192);
+  const long long N = (long long)p.nx * p.ny * p.nz;
+  cfg.cell_grid = (int)std::max<long long>(1, std::min<long long>((N + 255) / 256, 4096));
+  cfg.with_mass = 1;
+  return cfg;
+}
+
+// host-side conversions for uploads
+template <class T>
+std::vector<char> pack_real(const std::vector<double> &v, int bytes) {
+  (void)sizeof(T);
+  std::vector<char> out(v.size() * bytes);
+  if (bytes == 8) {
+    std::memcpy(out.data(), v.data(), v.size() * 8);
+  } else {
+    float *o = (float *)out.data();
+    for (size_t k = 0; k < v.size(); ++k) o[k] = (float)v[k];
+  }
+  return out;
+}
+
+int sync_and_check(Ctx &c) {
+  HIP_TRY(hipStreamSynchronize(c.stream));
+  Scalars sc;
+  HIP_TRY(hipMemcpy(&sc, c.dev[0].sc, sizeof sc, hipMemcpyDeviceToHost));
+  if (sc.err & ERR_CAPACITY) return fail(FSLBM_ECAPACITY, "bubble table full (max_bubbles)");
+  if (sc.err & ERR_NONFINITE) return fail(FSLBM_ENUMERIC, "non-finite total mass");
+  return FSLBM_OK;
+}
+
+}  // namespace
+
+// ==================================================================== ABI
+
+extern "C" {
+
+const char *fslbm_last_error(void) { return g_err.c_str(); }
+
+size_t fslbm_workspace_bytes(const fslbm_params *params) {
+  if (check_params(params)) return 0;
+  Launchers L;
+  if (!launchers_for(params->precision, L)) return 0;
+  return make_layout(*params, L).total;
+}
+
+int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const double *phi,
+                 const double *rho, const double *u, const int32_t *bubble_id,
+                 const fslbm_bubble_init *bubbles, int32_t n_bubbles, const double *f_init,
+                 const double *mass_init, const fslbm_scalars *restore, void *device_workspace,
+                 size_t workspace_bytes, void *stream, void **out_handle) {
+  if (!out_handle) return fail(FSLBM_EINVAL, "out_handle is NULL");
+  *out_handle = nullptr;
+  if (const char *m = check_params(params)) return fail(FSLBM_EINVAL, m);
+  const fslbm_params &p = *params;
+  if (!cell_type || !phi || !rho || !u || !bubble_id || (n_bubbles > 0 && !bubbles))
+    return fail(FSLBM_EINVAL, "an input array is NULL");
+  if (n_bubbles < 0 || n_bubbles > p.max_bubbles)
+    return fail(FSLBM_EINVAL, "n_bubbles out of range (max_bubbles)");
+  Launchers L;
+  launchers_for(p.precision, L);
+  const Layout lay = make_layout(p, L);
+  if (!device_workspace) return fail(FSLBM_EINVAL, "device_workspace is NULL");
+  if (((uintptr_t)device_workspace) % 256 != 0)
+    return fail(FSLBM_EINVAL, "device_workspace must be 256-byte aligned");
+  if (workspace_bytes < lay.total)
+    return fail(FSLBM_ENOMEM, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const long long N = (long long)nx * ny * nz;
+  const int n3[3] = {nx, ny, nz};
+  auto nb = [&](long long i, int a) -> long long {
+    int c[3] = {(int)(i % nx), (int)((i / nx) % ny), (int)(i / ((long long)nx * ny))};
+    const int dc[3] = {HOST_CX[a], HOST_CY[a], HOST_CZ[a]};
+    for (int k = 0; k < 3; ++k) {
+      c[k] += dc[k];
+      if (p.periodic[k]) c[k] = (c[k] % n3[k] + n3[k]) % n3[k];
+      if (c[k] < 0 || c[k] >= n3[k]) return -1;
+    }
+    return c[0] + (long long)nx * (c[1] + (long long)ny * c[2]);
+  };
+  auto gasreg = [](uint8_t t) { return t == T_GAS || t == T_IFACE || t == T_INLET; };
+
+  // ---- validation (same rules as the problem statement: closed interface
+  // layer, walls only on non-periodic faces, consistent bubble IDs)
+  std::vector<int> slot_of_index(n_bubbles);
+  int32_t max_id = -1;
+  for (int k = 0; k < n_bubbles; ++k) {
+    if (bubbles[k].id < 0) return fail(FSLBM_EINVAL, "bubble IDs must be >= 0");
+    for (int j = 0; j < k; ++j)
+      if (bubbles[j].id == bubbles[k].id) return fail(FSLBM_EINVAL, "duplicate bubble ID");
+    max_id = std::max(max_id, bubbles[k].id);
+  }
+  auto slot_of_id = [&](int32_t id) -> int {
+    for (int k = 0; k < n_bubbles; ++k)
+      if (bubbles[k].id == id) return k;
+    return -1;
+  };
+  std::vector<uint8_t> flag(N);
+  std::vector<int32_t> bslot(N, -1);
+  char msg[256];
+  for (long long i = 0; i < N; ++i) {
+    const uint8_t t = cell_type[i];
+    const int c[3] = {(int)(i % nx), (int)((i / nx) % ny), (int)(i / ((long long)nx * ny))};
+    if (t > T_INLET) {
+      snprintf(msg, sizeof msg, "cell %lld: unknown type %d", i, t);
+      return fail(FSLBM_EINVAL, msg);
+    }
+    bool face = false;
+    for (int k = 0; k < 3; ++k)
+      if (!p.periodic[k] && (c[k] == 0 || c[k] == n3[k] - 1)) face = true;
+    if (face && t != T_WALL && t != T_INLET) {
+      snprintf(msg, sizeof msg, "cell %lld: non-periodic face layer must be wall or inlet", i);
+      return fail(FSLBM_EINVAL, msg);
+    }
+    if (!face && t == T_WALL) {
+      snprintf(msg, sizeof msg, "cell %lld: walls only on non-periodic face layers", i);
+      return fail(FSLBM_EINVAL, msg);
+    }
+    if (t == T_IFACE && !(phi[i] >= -0.1 && phi[i] <= 1.1)) {
+      snprintf(msg, sizeof msg, "cell %lld: interface fill level out of range", i);
+      return fail(FSLBM_EINVAL, msg);
+    }
+    if ((t == T_IFACE || t == T_LIQ) && !(rho[i] > 0.0)) {
+      snprintf(msg, sizeof msg, "cell %lld: density must be positive", i);
+      return fail(FSLBM_EINVAL, msg);
+    }
+    if (gasreg(t)) {
+      const int s = slot_of_id(bubble_id[i]);
+      if (s < 0) {
+        snprintf(msg, sizeof msg, "cell %lld: bubble ID %d not listed", i, bubble_id[i]);
+        return fail(FSLBM_EINVAL, msg);
+      }
+      bslot[i] = s;
+    }
+    uint8_t f = t;
+    for (int a = 1; a < Q; ++a) {
+      const long long j = nb(i, a);
+      if (j < 0) continue;
+      const uint8_t tj = cell_type[j];
+      if (tj == T_WALL) f |= NEAR_WALL;
+      if (tj == T_INLET) f |= NEAR_INLET;
+      if (t == T_LIQ && (tj == T_GAS || tj == T_INLET)) {
+        snprintf(msg, sizeof msg, "cell %lld: liquid next to gas", i);
+        return fail(FSLBM_EINVAL, msg);
+      }
+      if (gasreg(t) && gasreg(tj) && bubble_id[i] != bubble_id[j]) {
+        snprintf(msg, sizeof msg, "cells %lld/%lld: touching gas cells with different IDs", i, j);
+        return fail(FSLBM_EINVAL, msg);
+      }
+    }
+    flag[i] = f;
+  }
+
+  // ---- initial bubble table (volumes summed in cell order)
+  const int B = p.max_bubbles;
+  std::vector<int32_t> b_id(B, 0), b_flags(B, 0), b_live(B, 0);
+  std::vector<double> b_vol(B, 0.0), b_vstar(B, 0.0), b_p(B, 0.0);
+  std::vector<long long> b_ngas(B, 0), b_niface(B, 0);
+  // exactly rounded volume sums, as in every step
+  std::vector<long long> vw((size_t)B * EX_WORDS, 0);
+  for (long long i = 0; i < N; ++i) {
+    const uint8_t t = cell_type[i];
+    if (!gasreg(t)) continue;
+    const int s = bslot[i];
+    const ExTerm term = ex_split(t == T_IFACE ? 1.0 - phi[i] : 1.0);
+    for (int c = 0; c < EX_WORDS; ++c) vw[(size_t)s * EX_WORDS + c] += term.w[c];
+    if (t == T_IFACE) b_niface[s] += 1;
+    else b_ngas[s] += 1;
+  }
+  for (int s = 0; s < n_bubbles; ++s) b_vol[s] = ex_value(&vw[(size_t)s * EX_WORDS]);
+  for (int k = 0; k < n_bubbles; ++k) {
+    b_id[k] = bubbles[k].id;
+    b_flags[k] = bubbles[k].flags & FSLBM_BUBBLE_INLET;
+    b_live[k] = 1;
+    b_vstar[k] = bubbles[k].v_star > 0.0 ? bubbles[k].v_star : b_vol[k] * bubbles[k].p_init / p.p0;
+    const double v = b_vol[k] > 1e-2 ? b_vol[k] : 1e-2;
+    b_p[k] = p.p0 * b_vstar[k] / v;
+  }
+
+  // ---- fields
+  std::vector<double> phi_h(N), mass_h(N), rhoi_h(N, 0.0);
+  long long n_iface = 0;
+  long long Mw[EX_WORDS] = {0, 0, 0, 0, 0};
+  auto madd = [&](double v) {
+    const ExTerm t = ex_split(v);
+    for (int c = 0; c < EX_WORDS; ++c) Mw[c] += t.w[c];
+  };
+  for (long long i = 0; i < N; ++i) {
+    const uint8_t t = cell_type[i];
+    if (t == T_IFACE) {
+      phi_h[i] = phi[i];
+      mass_h[i] = mass_init ? mass_init[i] : phi[i] * rho[i];
+      rhoi_h[i] = rho[i];
+      madd(mass_h[i]);
+      ++n_iface;
+    } else if (t == T_LIQ) {
+      phi_h[i] = 1.0;
+      mass_h[i] = rho[i];
+      madd(mass_h[i]);
+    } else {
+      phi_h[i] = 0.0;
+      mass_h[i] = 0.0;
+    }
+  }
+
+  Ctx *c = new Ctx();
+  c->P = p;
+  c->L = L;
+  c->cfg = make_cfg(p);
+  c->lay = lay;
+  c->N = N;
+  c->stream = (hipStream_t)stream;
+  c->ws = (char *)device_workspace;
+  build_devs(*c);
+  c->cur = 0;
+  const Dev &d = c->dev[0];
+  hipStream_t st = c->stream;
+  auto cleanup_fail = [&](int code) {
+    delete c;
+    return code;
+  };
+#define UP(dst, src, bytes) \
+  do { hipError_t e_ = hipMemcpyAsync((dst), (src), (bytes), hipMemcpyHostToDevice, st); \
+       if (e_ != hipSuccess) { fail(FSLBM_EDEVICE, std::string("upload: ") + hipGetErrorString(e_)); \
+                               return cleanup_fail(FSLBM_EDEVICE); } } while (0)
+  // zero everything first (not captured in any graph)
+  {
+    hipError_t e = hipMemsetAsync(c->ws, 0, lay.total, st);
+    if (e != hipSuccess) {
+      fail(FSLBM_EDEVICE, std::string("memset: ") + hipGetErrorString(e));
+      return cleanup_fail(FSLBM_EDEVICE);
+    }
+  }
+  UP(d.flag_src, flag.data(), N);
+  UP(d.flag_dst, flag.data(), N);
+  std::vector<char> phi_p = pack_real<double>(phi_h, L.real_bytes);
+  std::vector<char> mass_p = pack_real<double>(mass_h, L.real_bytes);
+  std::vector<char> rhoi_p = pack_real<double>(rhoi_h, L.real_bytes);
+  UP(d.phi_src, phi_p.data(), phi_p.size());
+  UP(d.phi_dst, phi_p.data(), phi_p.size());
+  UP(d.mass, mass_p.data(), mass_p.size());
+  UP(d.rhoI, rhoi_p.data(), rhoi_p.size());
+  UP(d.bslot, bslot.data(), N * 4);
+  UP(d.b_id, b_id.data(), B * 4);
+  UP(d.b_flags, b_flags.data(), B * 4);
+  UP(d.b_live, b_live.data(), B * 4);
+  UP(d.b_vol, b_vol.data(), B * 8);
+  UP(d.b_vstar, b_vstar.data(), B * 8);
+  UP(d.b_p, b_p.data(), B * 8);
+  UP(d.b_ngas, b_ngas.data(), B * 8);
+  UP(d.b_niface, b_niface.data(), B * 8);
+  Scalars sc{};
+  sc.step = restore ? restore->step : 0;
+  sc.next_id = std::max(restore ? restore->next_id : 0, max_id + 1);
+  sc.bucket = restore ? restore->bucket : 0.0;
+  sc.n_iface = n_iface;
+  sc.share = n_iface > 0 ? sc.bucket / (double)n_iface : 0.0;
+  madd(sc.bucket);
+  sc.total_mass = ex_value(Mw);
+  sc.n_live = n_bubbles;
+  sc.label_run = 1;  // the first step labels the gas region
+  UP(d.sc, &sc, sizeof sc);
+  // PDFs, through the destination lattice as FP64 staging
+  double *staging = (double *)d.f_dst;
+  if (f_init) {
+    for (int a = 0; a < Q; ++a) {
+      UP(staging, f_init + (size_t)a * N, N * 8);
+      c->L.init_f(d, c->cfg, staging, a, st);
+    }
+  } else {
+    UP(staging, rho, N * 8);
+    UP(staging + N, u, 3 * N * 8);
+    c->L.init_feq(d, c->cfg, staging, staging + N, st);
+  }
+  {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+      fail(FSLBM_EDEVICE, std::string("create: ") + hipGetErrorString(e));
+      return cleanup_fail(FSLBM_EDEVICE);
+    }
+  }
+#undef UP
+  *out_handle = c;
+  g_err.clear();
+  return FSLBM_OK;
+}
+
+int fslbm_step(void *handle, int32_t n_steps) {
+  if (!handle) return fail(FSLBM_EINVAL, "handle is NULL");
+  if (n_steps < 0) return fail(FSLBM_EINVAL, "n_steps < 0");
+  Ctx &c = *(Ctx *)handle;
+  for (int s = 0; s < n_steps; ++s) {
+    const Dev &d = c.dev[c.cur];
+    if (c.timing) {
+      while (c.events.size() < c.used + PH_COUNT + 1) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        c.events.push_back(e);
+      }
+      HIP_TRY(hipEventRecord(c.events[c.used], c.stream));
+      for (int ph = 0; ph < PH_COUNT; ++ph) {
+        c.L.phase(ph, d, c.cfg, c.stream);
+        HIP_TRY(hipEventRecord(c.events[c.used + 1 + ph], c.stream));
+      }
+      c.used += PH_COUNT + 1;
+    } else {
+      for (int ph = 0; ph < PH_COUNT; ++ph) c.L.phase(ph, d, c.cfg, c.stream);
+    }
+    c.cur ^= 1;
+  }
+  HIP_TRY(hipGetLastError());
+  return FSLBM_OK;
+}
+
+int fslbm_set_timing(void *handle, int32_t enable) {
+  if (!handle) return fail(FSLBM_EINVAL, "handle is NULL");
+  Ctx &c = *(Ctx *)handle;
+  c.timing = enable != 0;
+  c.used = 0;
+  return FSLBM_OK;
+}
+
+int fslbm_get_timing(void *handle, fslbm_timing *out) {
+  if (!handle || !out) return fail(FSLBM_EINVAL, "NULL argument");
+  Ctx &c = *(Ctx *)handle;
+  HIP_TRY(hipStreamSynchronize(c.stream));
+  double ms[PH_COUNT] = {0};
+  const size_t per = PH_COUNT + 1;
+  const size_t nsteps = c.used / per;
+  for (size_t s = 0; s < nsteps; ++s)
+    for (int ph = 0; ph < PH_COUNT; ++ph) {
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, c.events[s * per + ph], c.events[s * per + ph + 1]));
+      ms[ph] += t;
+    }
+  out->steps = (int64_t)nsteps;
+  out->bulk_ms = ms[PH_BULK];
+  out->iface_ms = ms[PH_IFACE];
+  out->convert_ms = ms[PH_CONVERT];
+  out->excess_ms = ms[PH_EXCESS];
+  out->gather_ms = ms[PH_GATHER];
+  out->label_ms = ms[PH_LABEL];
+  out->bubbles_ms = ms[PH_BUBBLES];
+  double tot = 0.0;
+  for (int ph = 0; ph < PH_COUNT; ++ph) tot += ms[ph];
+  out->step_ms = tot;
+  c.used = 0;
+  return FSLBM_OK;
+}
+
+int fslbm_sync(void *handle) {
+  if (!handle) return fail(FSLBM_EINVAL, "handle is NULL");
+  return sync_and_check(*(Ctx *)handle);
+}
+
+int fslbm_read_fields(void *handle, uint8_t *cell_type, double *phi, double *mass, double *f,
+                      int32_t *bubble_id, double *rho, double *u, fslbm_scalars *scalars) {
+  if (!handle) return fail(FSLBM_EINVAL, "handle is NULL");
+  Ctx &c = *(Ctx *)handle;
+  int rc = sync_and_check(c);
+  if (rc != FSLBM_OK) return rc;
+  const Dev &d = c.dev[c.cur];
+  const long long N = c.N;
+  double *staging = (double *)d.f_dst;
+  auto fetch = [&](int what, double *out) -> int {
+    c.L.exportq(d, c.cfg, staging, what, c.stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, staging, N * 8, hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    return FSLBM_OK;
+  };
+  if (cell_type) {
+    HIP_TRY(hipMemcpy(cell_type, d.flag_src, N, hipMemcpyDeviceToHost));
+    for (long long i = 0; i < N; ++i) cell_type[i] &= TYPE_MASK;
+  }
+  if (phi && (rc = fetch(0, phi))) return rc;
+  if (mass && (rc = fetch(1, mass))) return rc;
+  if (rho && (rc = fetch(2, rho))) return rc;
+  if (u)
+    for (int k = 0; k < 3; ++k)
+      if ((rc = fetch(3 + k, u + k * N))) return rc;
+  if (f)
+    for (int a = 0; a < Q; ++a)
+      if ((rc = fetch(6 + a, f + (size_t)a * N))) return rc;
+  if (bubble_id) {
+    std::vector<int32_t> slot(N), ids(c.P.max_bubbles);
+    HIP_TRY(hipMemcpy(slot.data(), d.bslot, N * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ids.data(), d.b_id, c.P.max_bubbles * 4, hipMemcpyDeviceToHost));
+    std::vector<uint8_t> t(N);
+    HIP_TRY(hipMemcpy(t.data(), d.flag_src, N, hipMemcpyDeviceToHost));
+    for (long long i = 0; i < N; ++i) {
+      const uint8_t ty = t[i] & TYPE_MASK;
+      const bool g = ty == T_GAS || ty == T_IFACE || ty == T_INLET;
+      bubble_id[i] = (g && slot[i] >= 0) ? ids[slot[i]] : -1;
+    }
+  }
+  if (scalars) {
+    Scalars sc;
+    HIP_TRY(hipMemcpy(&sc, d.sc, sizeof sc, hipMemcpyDeviceToHost));
+    scalars->step = sc.step;
+    scalars->next_id = sc.next_id;
+    scalars->n_bubbles = sc.n_live;
+    scalars->bucket = sc.bucket;
+    scalars->total_mass = sc.total_mass;
+    scalars->n_topology = sc.n_topology;
+  }
+  return FSLBM_OK;
+}
+
+int fslbm_bubbles(void *handle, fslbm_bubble *out, int32_t capacity, int32_t *n_out) {
+  if (!handle) return fail(FSLBM_EINVAL, "handle is NULL");
+  Ctx &c = *(Ctx *)handle;
+  int rc = sync_and_check(c);
+  if (rc != FSLBM_OK) return rc;
+  const Dev &d = c.dev[c.cur];
+  const int B = c.P.max_bubbles;
+  std::vector<int32_t> id(B), fl(B), live(B);
+  std::vector<double> vol(B), vs(B), pr(B);
+  std::vector<long long> ng(B), ni(B);
+  HIP_TRY(hipMemcpy(id.data(), d.b_id, B * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(fl.data(), d.b_flags, B * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(live.data(), d.b_live, B * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(vol.data(), d.b_vol, B * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(vs.data(), d.b_vstar, B * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(pr.data(), d.b_p, B * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(ng.data(), d.b_ngas, B * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(ni.data(), d.b_niface, B * 8, hipMemcpyDeviceToHost));
+  std::vector<fslbm_bubble> v;
+  for (int s = 0; s < B; ++s)
+    if (live[s]) v.push_back(fslbm_bubble{id[s], fl[s], vol[s], vs[s], pr[s], ng[s] + ni[s]});
+  std::sort(v.begin(), v.end(), [](const fslbm_bubble &a, const fslbm_bubble &b) { return a.id < b.id; });
+  if (n_out) *n_out = (int32_t)v.size();
+  if ((int32_t)v.size() > capacity) return fail(FSLBM_ECAPACITY, "output capacity too small");
+  if (out) std::copy(v.begin(), v.end(), out);
+  return FSLBM_OK;
+}
+
+int fslbm_destroy(void *handle) {
+  if (!handle) return fail(FSLBM_EINVAL, "handle is NULL");
+  Ctx *c = (Ctx *)handle;
+  hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->events) hipEventDestroy(e);
+  delete c;
+  return FSLBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Device-side data layout shared by the host API and the kernels of the
+// MI355X FSLBM library.  Nothing here is visible across the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "exactsum.hpp"
+
+namespace fslbm {
+
+constexpr int Q = 19;
+
+// Cell type in the low three bits of the flag byte (values of the C ABI).
+constexpr uint8_t T_GAS = 0, T_IFACE = 1, T_LIQ = 2, T_WALL = 3, T_INLET = 4;
+constexpr uint8_t TYPE_MASK = 0x07;
+// Static bits, fixed at creation: the cell has a wall / an inlet cell among
+// its 18 neighbours.
+constexpr uint8_t NEAR_WALL = 0x08;
+constexpr uint8_t NEAR_INLET = 0x10;
+constexpr uint8_t STATIC_BITS = NEAR_WALL | NEAR_INLET;
+// Conversion candidates written by the interface kernel for its new state:
+// fill level above 1 + eps (and no inlet neighbour), below -eps.
+constexpr uint8_t CAND_F = 0x20;
+constexpr uint8_t CAND_E = 0x40;
+
+// Accumulator replication: atomics of one logical sum are spread over SUB
+// slots (picked by block index) to avoid serialising on one address; the
+// slots are integers, so the final sum is independent of order.
+constexpr int SUB = 16;
+constexpr int SUB_MASS = 256;
+
+// Fixed-point scale of the two-word integer accumulator of the total mass
+// diagnostic (value * 2^FX_VOL rounded to an int64, split into a high and a
+// low word); |term| < 2^13.
+constexpr int FX_VOL = 50;
+constexpr int FX_SPLIT = 25;
+
+// Per-bubble accumulator: exact-sum words of the gas volume, then the
+// interface-cell count.
+constexpr int VACC = EX_WORDS + 1;
+// Per-new-component accumulators of a labelling event: exact-sum words of
+// the volume and of V*, then ncells, ngas, niface, inlet cells.
+constexpr int NACC = 2 * EX_WORDS + 4;
+
+struct Scalars {
+  long long step;
+  long long n_iface;     // interface cells at the end of the last step
+  long long n_topology;  // steps with a labelling run
+  double bucket;         // orphan excess mass after the last step's phase D
+  double share;          // bucket / n_iface, added to every interface cell next step
+  double total_mass;
+  int next_id;
+  int n_live;
+  int label_run;         // labelling requested for the current step
+  int err;               // ERR_* bits
+  int nnew;              // new components of the current labelling run
+  int nfree;
+};
+constexpr int ERR_CAPACITY = 1;
+constexpr int ERR_NONFINITE = 2;
+constexpr int ERR_RANGE = 4;
+
+// Everything a kernel needs, passed by value.  src/dst refer to time t and
+// t+1 of the current step.
+struct Dev {
+  int nx, ny, nz;
+  int per[3];
+  int has_walls;
+  int max_bubbles;
+  int force_topology;
+  int collision;
+  long long N;
+  double omega_p, omega_m;
+  double sigma, p0, eps, inject;
+  double g[3];
+  // fields
+  void *f_src, *f_dst;
+  uint8_t *flag_src, *flag_dst;
+  void *phi_src, *phi_dst;
+  void *mass, *rhoI, *excess;
+  int32_t *bslot;
+  int32_t *lab, *aux0, *aux1, *aux2;
+  // bubble table, indexed by slot
+  int32_t *b_id, *b_flags, *b_live;
+  double *b_vstar, *b_vol, *b_p, *b_ratio;
+  long long *b_ngas, *b_niface;
+  int32_t *b_rmin, *b_rmax, *b_kept;
+  unsigned long long *b_vacc;   // [B][SUB][VACC]
+  unsigned long long *c_acc;    // [B][NACC] per new component
+  int32_t *newroots;            // [B]
+  int32_t *newslot;             // [B]
+  // scalars and global accumulators
+  Scalars *sc;
+  unsigned long long *mass_acc;   // [SUB_MASS][2]
+  unsigned long long *bucket_acc; // [SUB][EX_WORDS]
+  unsigned long long *niface_acc; // [SUB]
+};
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ void fx_split(double v, int scale, long long &hi, long long &lo) {
+  long long q = __double2ll_rn(ldexp(v, scale));
+  hi = q >> FX_SPLIT;
+  lo = q - (hi << FX_SPLIT);
+}
+
+__host__ __device__ inline double fx_value(long long hi, long long lo, int scale) {
+  return ldexp((double)hi, FX_SPLIT - scale) + ldexp((double)lo, -scale);
+}
+
+__device__ __forceinline__ long long wave_sum(long long v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Adds the NV values of every active lane (key >= 0) into
+// base[(key * stride + sub) * NV + k], one atomic per distinct key per wave.
+// Every lane of the wave must call it.
+template <int NV>
+__device__ __forceinline__ void wave_add_by_key(int key, const long long *v,
+                                                unsigned long long *base, int stride, int sub) {
+  bool active = key >= 0;
+  unsigned long long m = __ballot(active);
+  const int lane = __lane_id();
+  while (m) {
+    int leader = __ffsll((long long)m) - 1;
+    int lkey = __shfl(key, leader, 64);
+    bool mine = active && key == lkey;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      long long s = wave_sum(mine ? v[k] : 0ll);
+      if (lane == leader)
+        atomicAdd(&base[((long long)lkey * stride + sub) * NV + k], (unsigned long long)s);
+    }
+    unsigned long long mm = __ballot(mine);
+    if (mine) active = false;
+    m &= ~mm;
+  }
+}
+
+}  // namespace fslbm

@@ -308,6 +308,37 @@ def threads(n=(64, 64, 256), axes=((32.0, 32.0),), R=8.0, amp=0.1, wavelength=72
                    meta=dict(axes=ax.tolist(), R=R, amp=amp, wavelength=wavelength))
 
 
+def thread_lattice(n=(256, 256, 256), spacing=64, R=8.0, amp=0.1, wavelength=72.0,
+                   tau=0.55, sigma=5e-3, noise=1e-3, seed=256, steps=4000, name="lattice"):
+    """Gas threads along z on a square lattice: axes at (spacing/2 + k spacing,
+    spacing/2 + l spacing), each with the geometry of ``threads`` and its own
+    bubble ID (k + l * number of columns).  One spacing x spacing tile is
+    built and replicated, then the fill-level noise is drawn for the whole
+    box from one seeded generator."""
+    nx, ny, nz = n
+    assert nx % spacing == 0 and ny % spacing == 0
+    tile = threads(n=(spacing, spacing, nz), axes=((spacing / 2.0, spacing / 2.0),), R=R, amp=amp,
+                   wavelength=wavelength, tau=tau, sigma=sigma, noise=0.0, steps=steps)
+    kx, ky = nx // spacing, ny // spacing
+    t3 = np.tile(tile.cell_type.reshape(nz, spacing, spacing), (1, ky, kx))
+    p3 = np.tile(tile.phi.reshape(nz, spacing, spacing), (1, ky, kx))
+    t = t3.ravel()
+    phi = p3.ravel().copy()
+    if noise > 0.0:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        r = rng.uniform(-noise, noise, size=len(phi))
+        phi = np.where(t == IFACE, np.clip(phi + r, 0.0, 1.0), phi)
+    x, y, z = _grid(nx, ny, nz)
+    col = (x // spacing) + kx * (y // spacing)
+    setc = (t == GAS) | (t == IFACE)
+    bid = np.where(setc, col, -1).astype(np.int32)
+    N = nx * ny * nz
+    return Scene(name, nx, ny, nz, (1, 1, 1), tau, sigma, (0.0, 0.0, 0.0), 1e-2, 0.0,
+                 t.astype(np.uint8), phi, np.full(N, 1.0 - 3.0 * sigma / R), np.zeros(3 * N), bid,
+                 [(b, 0, -1.0, P0) for b in range(kx * ky)], steps,
+                 dict(spacing=spacing, R=R, amp=amp, wavelength=wavelength))
+
+
 def orifice(n=(128, 128, 256), r=6.0, g=1e-5, tau=0.6, sigma=2e-3, Q=0.05, steps=50000,
             name="orifice"):
     """Closed box with wall layers on all faces; the bottom wall is pierced by
@@ -355,8 +386,7 @@ def config(name: str) -> Scene:
     if name == "c3":
         return orifice(name="c3")
     if name == "p1":
-        axes = [(float(a), float(b)) for b in (32, 96, 160, 224) for a in (32, 96, 160, 224)]
-        return threads(n=(256, 256, 256), axes=axes, seed=256, steps=4000, name="p1")
+        return thread_lattice(n=(256, 256, 256), spacing=64, seed=256, steps=4000, name="p1")
     if name == "p0":
         return spheres(n=(256, 256, 256), centers=(), radii=(), name="p0", steps=4000,
                        rho_l=1.0, tau=0.55)

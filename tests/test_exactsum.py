@@ -1,0 +1,117 @@
+"""The GPU library's order-independent summation (exactsum.hpp, built for
+the host with g++) returns the correctly rounded exact sum, the same value
+as math.fsum, for every order and grouping of the terms."""
+import math
+import os
+import random
+import struct
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1604_01632_amd", "csrc")
+
+HARNESS = r"""
+#include <cstdio>
+#include <cstdint>
+#include <cstring>
+#include "exactsum.hpp"
+using namespace fslbm;
+int main() {
+  int n;
+  while (std::scanf("%d", &n) == 1) {
+    long long acc[EX_WORDS] = {0};
+    for (int k = 0; k < n; ++k) {
+      unsigned long long bits;
+      std::scanf("%llx", &bits);
+      double v;
+      std::memcpy(&v, &bits, 8);
+      ExTerm t = ex_split(v);
+      for (int c = 0; c < EX_WORDS; ++c) acc[c] += t.w[c];
+    }
+    double r = ex_value(acc);
+    unsigned long long o;
+    std::memcpy(&o, &r, 8);
+    std::printf("%016llx\n", o);
+  }
+  return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("exsum")
+    src = d / "h.cpp"
+    src.write_text(HARNESS)
+    exe = d / "h"
+    subprocess.run(["g++", "-O2", "-std=c++17", f"-I{CSRC}", str(src), "-o", str(exe)], check=True)
+    return str(exe)
+
+
+def _hex(v):
+    return format(struct.unpack("<Q", struct.pack("<d", v))[0], "016x")
+
+
+def _run(exe, cases):
+    inp = "".join(f"{len(c)} " + " ".join(_hex(v) for v in c) + "\n" for c in cases)
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split()
+    return [struct.unpack("<d", struct.pack("<Q", int(h, 16)))[0] for h in out]
+
+
+def test_matches_fsum_random(harness):
+    rng = random.Random(1)
+    cases = []
+    for k in range(400):
+        n = rng.randint(1, 300)
+        kind = k % 4
+        if kind == 0:
+            c = [rng.uniform(-1.1, 1.1) for _ in range(n)]
+        elif kind == 1:
+            c = [1.0 - rng.random() ** 8 for _ in range(n)] + [float(rng.randint(0, 5000))]
+        elif kind == 2:
+            c = [rng.uniform(-1, 1) * 2.0 ** rng.randint(-60, 30) for _ in range(n)]
+        else:
+            base = [rng.uniform(-1, 1) * 2.0 ** rng.randint(-40, 20) for _ in range(n)]
+            c = base + [-v for v in base[: n // 2]] + [2.0 ** -50, -(2.0 ** -51)]
+        cases.append(c)
+    got = _run(harness, cases)
+    for c, g in zip(cases, got):
+        assert g == math.fsum(c), (c[:5], g, math.fsum(c))
+    # order independence
+    c = cases[7]
+    perms = [c[::-1], sorted(c), sorted(c, key=abs)]
+    assert len(set(_run(harness, perms))) == 1
+
+
+def test_rounding_ties_and_cancellation(harness):
+    cases = [
+        [1.0, 2.0 ** -53],                 # tie -> even (1.0)
+        [1.0, 2.0 ** -53, 2.0 ** -60],     # above the tie -> up
+        [1.0 + 2.0 ** -52, 2.0 ** -53],    # tie -> even (up)
+        [1e10, 1.0, -1e10],
+        [2.0 ** 39, 2.0 ** 39, -(2.0 ** 39)],
+        [0.1] * 10,
+        [],
+        [-0.5, -0.25, -2.0 ** -60],
+    ]
+    got = _run(harness, cases)
+    for c, g in zip(cases, got):
+        assert g == math.fsum(c), (c, g)
+
+
+def test_oracle_fsum_matches_math_fsum(oracle_lib):
+    """The oracle's exactly rounded sum (Shewchuk partials) equals
+    math.fsum on random, ill-conditioned and tie cases."""
+    rng = random.Random(5)
+    cases = [[1.0, 2.0 ** -53], [1.0, 2.0 ** -53, 2.0 ** -60], [1.0 + 2.0 ** -52, 2.0 ** -53],
+             [1e10, 1.0, -1e10], [0.1] * 10, [], [-0.5, -0.25, -2.0 ** -60]]
+    for k in range(300):
+        n = rng.randint(1, 200)
+        c = [rng.uniform(-1, 1) * 2.0 ** rng.randint(-60, 40) for _ in range(n)]
+        if k % 3 == 0:
+            c += [-v for v in c[: n // 2]]
+        cases.append(c)
+    for c in cases:
+        assert oracle_lib.fsum(c) == math.fsum(c), c[:4]
