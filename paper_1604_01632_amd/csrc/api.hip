@@ -47,7 +47,7 @@ enum Arr {
   A_F0, A_F1, A_FLAG0, A_FLAG1, A_PHI0, A_PHI1, A_MASS, A_RHOI, A_EXCESS, A_BSLOT, A_LAB,
   A_AUX0, A_AUX1, A_AUX2, A_BID, A_BFLAGS, A_BLIVE, A_BRMIN, A_BRMAX, A_BKEPT, A_NEWROOTS,
   A_NEWSLOT, A_BVSTAR, A_BVOL, A_BP, A_BRATIO, A_BNGAS, A_BNIFACE, A_BVACC, A_CACC,
-  A_SCALARS, A_MASSACC, A_BUCKETACC, A_NIFACEACC, A_COUNT
+  A_SCALARS, A_MASSACC, A_BUCKETACC, A_ILIST0, A_ILIST1, A_CLIST, A_NLIST, A_MARK, A_GASV, A_NMASK, A_TILECOUNT, A_TILEOFF, A_COUNT
 };
 
 struct Layout {
@@ -73,7 +73,11 @@ Layout make_layout(const fslbm_params &p, const Launchers &L) {
   sz[A_SCALARS] = sizeof(Scalars);
   sz[A_MASSACC] = SUB_MASS * 2 * 8;
   sz[A_BUCKETACC] = SUB * EX_WORDS * 8;
-  sz[A_NIFACEACC] = SUB * 8;
+  sz[A_ILIST0] = sz[A_ILIST1] = sz[A_CLIST] = sz[A_NLIST] = N * 4;
+  sz[A_MARK] = ((N + 3) / 4) * 4;
+  sz[A_GASV] = N * L.real_bytes;
+  sz[A_NMASK] = N * 4;
+  sz[A_TILECOUNT] = sz[A_TILEOFF] = ((N + 4095) / 4096) * 4;
   Layout lay;
   size_t o = 0;
   for (int k = 0; k < A_COUNT; ++k) {
@@ -173,7 +177,13 @@ void build_devs(Ctx &c) {
   d.sc = at<Scalars>(ws, lay, A_SCALARS);
   d.mass_acc = at<unsigned long long>(ws, lay, A_MASSACC);
   d.bucket_acc = at<unsigned long long>(ws, lay, A_BUCKETACC);
-  d.niface_acc = at<unsigned long long>(ws, lay, A_NIFACEACC);
+  d.clist = at<int32_t>(ws, lay, A_CLIST);
+  d.nlist = at<int32_t>(ws, lay, A_NLIST);
+  d.mark = at<unsigned>(ws, lay, A_MARK);
+  d.gasv = ws + lay.off[A_GASV];
+  d.nmask = at<uint32_t>(ws, lay, A_NMASK);
+  d.tilecount = at<int32_t>(ws, lay, A_TILECOUNT);
+  d.tileoff = at<int32_t>(ws, lay, A_TILEOFF);
   for (int s = 0; s < 2; ++s) {
     Dev e = d;
     e.f_src = ws + lay.off[s == 0 ? A_F0 : A_F1];
@@ -182,6 +192,8 @@ void build_devs(Ctx &c) {
     e.flag_dst = at<uint8_t>(ws, lay, s == 0 ? A_FLAG1 : A_FLAG0);
     e.phi_src = ws + lay.off[s == 0 ? A_PHI0 : A_PHI1];
     e.phi_dst = ws + lay.off[s == 0 ? A_PHI1 : A_PHI0];
+    e.ilist_src = at<int32_t>(ws, lay, s == 0 ? A_ILIST0 : A_ILIST1);
+    e.ilist_dst = at<int32_t>(ws, lay, s == 0 ? A_ILIST1 : A_ILIST0);
     c.dev[s] = e;
   }
 }
@@ -189,10 +201,10 @@ void build_devs(Ctx &c) {
 LaunchCfg make_cfg(const fslbm_params &p) {
   LaunchCfg cfg;
   cfg.bx = p.nx >= 256 ? 256 : ((p.nx + 63) / 64) * 64;
-  const long long rows = (long long)p.ny * p.nz;
-  cfg.row_grid = (int)std::min<long long>(rows, 8192);
   const long long N = (long long)p.nx * p.ny * p.nz;
-  cfg.cell_grid = (int)std::max<long long>(1, std::min<long long>((N + 255) / 256, 4096));
+  cfg.list_grid = (int)std::max<long long>(1, std::min<long long>((N + 255) / 256, 2048));
+  cfg.small_grid = (int)std::max<long long>(1, std::min<long long>((N + 255) / 256, 256));
+  cfg.cell_grid = (int)std::max<long long>(1, std::min<long long>((N + 255) / 256, 1024));
   cfg.with_mass = 1;
   return cfg;
 }
@@ -371,6 +383,7 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
 
   // ---- fields
   std::vector<double> phi_h(N), mass_h(N), rhoi_h(N, 0.0);
+  std::vector<int32_t> ilist;
   long long n_iface = 0;
   long long Mw[EX_WORDS] = {0, 0, 0, 0, 0};
   auto madd = [&](double v) {
@@ -384,6 +397,7 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
       mass_h[i] = mass_init ? mass_init[i] : phi[i] * rho[i];
       rhoi_h[i] = rho[i];
       madd(mass_h[i]);
+      ilist.push_back((int32_t)i);
       ++n_iface;
     } else if (t == T_LIQ) {
       phi_h[i] = 1.0;
@@ -433,6 +447,7 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
   UP(d.mass, mass_p.data(), mass_p.size());
   UP(d.rhoI, rhoi_p.data(), rhoi_p.size());
   UP(d.bslot, bslot.data(), N * 4);
+  if (!ilist.empty()) UP(d.ilist_src, ilist.data(), ilist.size() * 4);
   UP(d.b_id, b_id.data(), B * 4);
   UP(d.b_flags, b_flags.data(), B * 4);
   UP(d.b_live, b_live.data(), B * 4);
@@ -451,6 +466,7 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
   sc.total_mass = ex_value(Mw);
   sc.n_live = n_bubbles;
   sc.label_run = 1;  // the first step labels the gas region
+  sc.n_il_src = (int)n_iface;
   UP(d.sc, &sc, sizeof sc);
   // PDFs, through the destination lattice as FP64 staging
   double *staging = (double *)d.f_dst;

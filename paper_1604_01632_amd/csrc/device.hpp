@@ -22,6 +22,9 @@ constexpr uint8_t STATIC_BITS = NEAR_WALL | NEAR_INLET;
 // fill level above 1 + eps (and no inlet neighbour), below -eps.
 constexpr uint8_t CAND_F = 0x20;
 constexpr uint8_t CAND_E = 0x40;
+// Set on interface cells of t+1 that receive excess mass from a converted
+// neighbour.
+constexpr uint8_t GATHER = 0x80;
 
 // Accumulator replication: atomics of one logical sum are spread over SUB
 // slots (picked by block index) to avoid serialising on one address; the
@@ -55,6 +58,10 @@ struct Scalars {
   int err;               // ERR_* bits
   int nnew;              // new components of the current labelling run
   int nfree;
+  int n_il_src;          // interface cells of time t (list length)
+  int n_il_dst;          // interface cells of t+1 appended so far
+  int n_cand;            // conversion candidates of the current step
+  int n_new;             // new interface cells of the current step
 };
 constexpr int ERR_CAPACITY = 1;
 constexpr int ERR_NONFINITE = 2;
@@ -89,11 +96,20 @@ struct Dev {
   unsigned long long *c_acc;    // [B][NACC] per new component
   int32_t *newroots;            // [B]
   int32_t *newslot;             // [B]
+  // cell lists: interface cells of t and t+1, conversion candidates, new
+  // interface cells; claim bits of the new-cell list (one byte per cell)
+  int32_t *ilist_src, *ilist_dst, *clist, *nlist;
+  unsigned *mark;
+  // per interface-list slot: gas density (FP64) or its deviation from 1,
+  // and the bit mask of directions to reconstruct
+  void *gasv;
+  uint32_t *nmask;
+  // per tile of the ordered interface-list build: counts and offsets
+  int32_t *tilecount, *tileoff;
   // scalars and global accumulators
   Scalars *sc;
   unsigned long long *mass_acc;   // [SUB_MASS][2]
   unsigned long long *bucket_acc; // [SUB][EX_WORDS]
-  unsigned long long *niface_acc; // [SUB]
 };
 
 // ---------------------------------------------------------------- helpers

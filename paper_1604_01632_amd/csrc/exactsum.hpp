@@ -17,6 +17,8 @@
 #endif
 #endif
 
+#define EX_INLINE inline __attribute__((always_inline))
+
 namespace fslbm {
 
 constexpr int EX_WORDS = 5;
@@ -27,8 +29,9 @@ struct ExTerm {
 };
 
 // Chunks of v * 2^EX_SCALE: chunk c holds bits [32c, 32c + 32).
-__host__ __device__ inline ExTerm ex_split(double v) {
+__host__ __device__ EX_INLINE ExTerm ex_split(double v) {
   ExTerm t;
+#pragma unroll
   for (int c = 0; c < EX_WORDS; ++c) t.w[c] = 0;
   if (v == 0.0 || v != v) return t;
   union {
@@ -55,6 +58,7 @@ __host__ __device__ inline ExTerm ex_split(double v) {
     s = 0;
   }
   const uint64_t MASK = 0xffffffffull;
+#pragma unroll
   for (int c = 0; c < EX_WORDS; ++c) {
     const int lo = 32 * c - s;  // lowest bit of m in this chunk
     uint64_t chunk;
@@ -68,10 +72,12 @@ __host__ __device__ inline ExTerm ex_split(double v) {
 }
 
 // Exact value of sum_c w[c] 2^(32c - EX_SCALE), rounded to nearest even.
-__host__ __device__ inline double ex_value(const long long *win) {
+__host__ __device__ EX_INLINE double ex_value(const long long *win) {
   long long w[EX_WORDS];
+#pragma unroll
   for (int c = 0; c < EX_WORDS; ++c) w[c] = win[c];
   // carry-normalise: w[0..3] in [0, 2^32), w[4] signed
+#pragma unroll
   for (int c = 0; c < EX_WORDS - 1; ++c) {
     const long long carry = w[c] >> 32;  // floor division by 2^32
     w[c] = w[c] & 0xffffffffll;       // the non-negative remainder
@@ -79,7 +85,7 @@ __host__ __device__ inline double ex_value(const long long *win) {
   }
   const bool neg = w[EX_WORDS - 1] < 0;
   // magnitude in three 64-bit limbs (bits 0..191)
-  uint64_t L[3];
+  uint64_t L[3] = {0, 0, 0};
   {
     // value = w4 * 2^128 + (w3 w2 w1 w0 in 32-bit digits)
     uint64_t lo = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
@@ -100,18 +106,34 @@ __host__ __device__ inline double ex_value(const long long *win) {
     L[1] = mid;
     L[2] = hi;
   }
-  int top = -1;
-  for (int k = 2; k >= 0 && top < 0; --k)
-    if (L[k]) top = 64 * k + 63 - __builtin_clzll(L[k]);
-  if (top < 0) return 0.0;
-  auto bit = [&](int j) -> uint64_t { return j < 0 ? 0ull : (L[j >> 6] >> (j & 63)) & 1ull; };
-  // 53 significant bits [top-52, top], round bit top-53, sticky below
-  uint64_t mant = 0;
-  for (int j = top; j >= top - 52; --j) mant = (mant << 1) | bit(j);
-  const uint64_t rbit = bit(top - 53);
+  // highest set bit
+  int top;
+  if (L[2]) top = 128 + 63 - __builtin_clzll(L[2]);
+  else if (L[1]) top = 64 + 63 - __builtin_clzll(L[1]);
+  else if (L[0]) top = 63 - __builtin_clzll(L[0]);
+  else return 0.0;
+  uint64_t mant, rbit = 0;
   bool sticky = false;
-  for (int j = top - 54; j >= 0 && !sticky; --j)
-    if (bit(j)) sticky = true;
+  const int sh = top - 52;  // bits below the 53 significant ones
+  if (sh <= 0) {
+    mant = L[0] << (-sh);  // the value fits in 53 bits (top < 64)
+  } else {
+    // mant = bits [sh, sh + 53); round bit sh - 1; sticky = bits below
+    const int q = sh >> 6, r = sh & 63;
+    const uint64_t a = q == 0 ? L[0] : (q == 1 ? L[1] : L[2]);
+    const uint64_t b = q == 0 ? L[1] : (q == 1 ? L[2] : 0ull);
+    mant = (r == 0 ? a : ((a >> r) | (b << (64 - r)))) & ((1ull << 53) - 1);
+    const int rb = sh - 1;
+    const int rq = rb >> 6, rr = rb & 63;
+    const uint64_t rl = rq == 0 ? L[0] : (rq == 1 ? L[1] : L[2]);
+    rbit = (rl >> rr) & 1ull;
+    // sticky: any bit below rb
+    const uint64_t below = rr == 0 ? 0ull : (rl & ((1ull << rr) - 1ull));
+    bool lower = false;
+    if (rq >= 1 && L[0]) lower = true;
+    if (rq >= 2 && L[1]) lower = true;
+    sticky = below != 0 || lower;
+  }
   if (rbit && (sticky || (mant & 1ull))) {
     mant += 1;
     if (mant == (1ull << 53)) {
@@ -122,7 +144,6 @@ __host__ __device__ inline double ex_value(const long long *win) {
   // value = mant * 2^(top - 52 - EX_SCALE)
   double r = (double)mant;
   int ex = top - 52 - EX_SCALE;
-  // scale by a power of two without rounding (|ex| is small)
   while (ex > 0) {
     const int k = ex > 60 ? 60 : ex;
     r *= (double)(1ull << k);

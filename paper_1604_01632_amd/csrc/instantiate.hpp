@@ -17,19 +17,26 @@ static void phase_impl(int ph, const Dev &d, const LaunchCfg &c, hipStream_t s) 
       break;
     }
     case PH_IFACE:
-      if (c.with_mass) k_iface<P, true><<<c.row_grid, 256, 0, s>>>(d);
-      else k_iface<P, false><<<c.row_grid, 256, 0, s>>>(d);
+      k_geom<P><<<c.list_grid, 256, 0, s>>>(d);
+      if (c.with_mass) k_iface<P, true><<<c.list_grid, 256, 0, s>>>(d);
+      else k_iface<P, false><<<c.list_grid, 256, 0, s>>>(d);
       break;
     case PH_CONVERT:
-      k_convert<P><<<c.row_grid, 256, 0, s>>>(d);
+      k_conv_types<P><<<c.small_grid, 256, 0, s>>>(d);
+      k_conv_init<P><<<c.small_grid, 256, 0, s>>>(d);
       break;
     case PH_EXCESS:
-      k_excess<P><<<c.row_grid, 256, 0, s>>>(d);
+      k_excess<P><<<c.small_grid, 256, 0, s>>>(d);
       break;
-    case PH_GATHER:
-      k_gather<P><<<c.row_grid, 256, 0, s>>>(d);
+    case PH_GATHER: {
+      k_gather<P><<<c.list_grid, 256, 0, s>>>(d);
+      const int ntiles = (int)((d.N + LTILE - 1) / LTILE);
+      k_list_count<<<ntiles, 256, 0, s>>>(d);
+      k_list_scan<<<1, 1024, 0, s>>>(d, ntiles);
+      k_list_fill<<<ntiles, 256, 0, s>>>(d);
       k_volumes<P><<<1, 1024, 0, s>>>(d);
       break;
+    }
     case PH_LABEL:
       k_label_init<<<c.cell_grid, 256, 0, s>>>(d);
       k_label_union<<<c.cell_grid, 256, 0, s>>>(d);

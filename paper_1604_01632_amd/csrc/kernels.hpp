@@ -2,22 +2,23 @@
 // bubble model (arXiv:1604.01632), templated on the storage precision.
 //
 // Step pipeline (one HIP stream, no host synchronisation):
-//   k_bulk       liquid cells: pull streaming with half-way bounce-back and
-//                collision (Sec. 2.1)
-//   k_iface      interface cells: Youngs normal and height-function
-//                curvature, gas pressure p_V + 2 sigma kappa (Sec. 2.2),
-//                reconstruction of gas-side PDFs, mass exchange, collision,
-//                fill level, conversion candidates
-//   k_convert    new cell types (closed interface layer) and initial values
-//                of new interface cells
-//   k_excess     excess mass of converted cells, bucket, topology trigger
-//   k_gather     interface cells pull excess mass; fill levels; per-bubble
-//                volume sums (Sec. 2.3)
-//   k_volumes    per-bubble volumes, bucket share, total mass
-//   k_label_*    union-find labelling of the gas region and the merge /
-//                split rules (Sec. 2.3.1, 2.3.2) - every kernel returns at
-//                once unless the trigger fired
-//   k_bubbles    injection and ideal-gas pressure (Sec. 2.2)
+//   k_bulk        liquid cells (dense grid): pull streaming with half-way
+//                 bounce-back and collision (Sec. 2.1)
+//   k_iface       interface cells (list): Youngs normal and height-function
+//                 curvature, gas pressure p_V + 2 sigma kappa (Sec. 2.2),
+//                 reconstruction of gas-side PDFs, mass exchange, collision,
+//                 fill level; conversion candidates appended to a list
+//   k_conv_types  new cell types (closed interface layer); new interface
+//                 cells appended to a list (each once)
+//   k_conv_init   initial values of the new interface cells
+//   k_excess      excess mass of converted cells, bucket, topology trigger
+//   k_gather      interface cells of t+1 pull excess mass; fill levels;
+//                 per-bubble volume sums (Sec. 2.3); next interface list
+//   k_volumes     per-bubble volumes, bucket share, total mass
+//   k_label_*     union-find labelling of the gas region and the merge /
+//                 split rules (Sec. 2.3.1, 2.3.2) - every kernel returns at
+//                 once unless the trigger fired
+//   k_bubbles     injection and ideal-gas pressure (Sec. 2.2)
 #pragma once
 #include <float.h>
 #include <limits.h>
@@ -79,22 +80,32 @@ __device__ __forceinline__ void st(void *f, int a, long long N, long long i, typ
 
 // ------------------------------------------------------------- geometry
 
+// Periodic wrap by adding or subtracting the extent (no integer division;
+// offsets are at most a few cells).
 __device__ __forceinline__ int wrap_axis(int c, int n, int per) {
   if (!per) return c;
-  c %= n;
-  return c < 0 ? c + n : c;
+  while (c < 0) c += n;
+  while (c >= n) c -= n;
+  return c;
 }
 
+// Periodic wrap of a coordinate at most one cell outside [0, n).
+__device__ __forceinline__ int wrap1(int c, int n, int per) {
+  if (!per) return c;
+  return c < 0 ? c + n : (c >= n ? c - n : c);
+}
+
+// Linear index; the number of cells is below 2^31 (checked at creation).
 __device__ __forceinline__ long long cidx(const Dev &d, int x, int y, int z) {
-  return (long long)x + (long long)d.nx * ((long long)y + (long long)d.ny * z);
+  return (long long)(x + d.nx * (y + d.ny * z));
 }
 
 // Neighbour of an interior cell (fluid and gas cells are interior on
 // non-periodic axes, whose face layers are walls or inlets).
 __device__ __forceinline__ long long nbr(const Dev &d, int x, int y, int z, int dx, int dy,
                                          int dz) {
-  return cidx(d, wrap_axis(x + dx, d.nx, d.per[0]), wrap_axis(y + dy, d.ny, d.per[1]),
-              wrap_axis(z + dz, d.nz, d.per[2]));
+  return cidx(d, wrap1(x + dx, d.nx, d.per[0]), wrap1(y + dy, d.ny, d.per[1]),
+              wrap1(z + dz, d.nz, d.per[2]));
 }
 
 // Neighbour of any cell, -1 outside the box on a non-periodic axis.
@@ -110,6 +121,30 @@ __device__ __forceinline__ long long nbr_checked(const Dev &d, int x, int y, int
 __device__ __forceinline__ bool in_gas_region(uint8_t t) {
   return t == T_GAS || t == T_IFACE || t == T_INLET;
 }
+
+__device__ __forceinline__ void coords(const Dev &d, long long i, int &x, int &y, int &z) {
+  const unsigned u = (unsigned)i, nx = (unsigned)d.nx, ny = (unsigned)d.ny;
+  const unsigned r = u / nx;
+  x = (int)(u - r * nx);
+  z = (int)(r / ny);
+  y = (int)(r - (unsigned)z * ny);
+}
+
+// Wrapped coordinates of the 27 cells around (x, y, z) (interior cells).
+struct Nb3 {
+  int xs[3], ys[3], zs[3];
+  __device__ __forceinline__ Nb3(const Dev &d, int x, int y, int z) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      xs[k] = wrap1(x + k - 1, d.nx, d.per[0]);
+      ys[k] = wrap1(y + k - 1, d.ny, d.per[1]);
+      zs[k] = wrap1(z + k - 1, d.nz, d.per[2]);
+    }
+  }
+  __device__ __forceinline__ long long at(const Dev &d, int dx, int dy, int dz) const {
+    return (long long)(xs[dx + 1] + d.nx * (ys[dy + 1] + d.ny * zs[dz + 1]));
+  }
+};
 
 // ------------------------------------------------------------ reductions
 
@@ -340,58 +375,50 @@ __device__ __forceinline__ void collide(const Dev &d, typename P::R *f, typename
 
 // -------------------------------------------------- interface geometry
 
-// Fill level seen by the geometry at integer position (x,y,z): periodic
-// axes wrap; samples on wall cells or outside the box take the value of
-// their mirror image across the wall plane (half-way between the wall layer
-// and the first fluid layer).
-template <class R>
-__device__ __forceinline__ R phi_sample(const Dev &d, const R *phi, int x, int y, int z) {
-  int c[3] = {x, y, z};
-  const int n[3] = {d.nx, d.ny, d.nz};
-#pragma unroll
-  for (int k = 0; k < 3; ++k) c[k] = wrap_axis(c[k], n[k], d.per[k]);
-  if (!d.has_walls) return phi[cidx(d, c[0], c[1], c[2])];
-  bool inside = true;
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-    if (c[k] < 0 || c[k] >= n[k]) inside = false;
-  if (inside) {
-    const long long i = cidx(d, c[0], c[1], c[2]);
-    if ((d.flag_src[i] & TYPE_MASK) != T_WALL) return phi[i];
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (d.per[k]) continue;
-    if (c[k] <= 0) c[k] = 1 - c[k];
-    else if (c[k] >= n[k] - 1) c[k] = 2 * n[k] - 3 - c[k];
-  }
-  return phi[cidx(d, c[0], c[1], c[2])];
-}
+// Parker-Youngs gradient of the fill level (weights 4/2/1 for face / edge /
+// corner offsets, pointing from gas into liquid) and the height-function
+// curvature are computed by k_geom from the cell's 3x3x3 neighbourhood.
 
-// Parker-Youngs gradient of the fill level, weights 4/2/1 for face / edge /
-// corner offsets; points from gas into liquid.
+// Fill-level samples at offsets -3..3 per axis from a cell: plain
+// coordinates (wrapped on periodic axes) and their mirror images across the
+// wall planes on non-periodic axes; a sample on a wall cell or outside the
+// box takes the mirrored cell (the rule of phi_sample).
 template <class R>
-__device__ __forceinline__ void youngs_normal(const Dev &d, const R *phi, int x, int y, int z,
-                                              R *n) {
-  n[0] = n[1] = n[2] = (R)0;
+struct PhiWin {
+  int xp[7], yp[7], zp[7], xm[7], ym[7], zm[7];
+  __device__ __forceinline__ PhiWin(const Dev &d, int x, int y, int z) {
 #pragma unroll
-  for (int p = -1; p <= 1; ++p)
-#pragma unroll
-    for (int q = -1; q <= 1; ++q) {
-      const R w = (R)((p == 0 ? 2 : 1) * (q == 0 ? 2 : 1));
-      n[0] += w * (phi_sample(d, phi, x + 1, y + p, z + q) - phi_sample(d, phi, x - 1, y + p, z + q));
-      n[1] += w * (phi_sample(d, phi, x + p, y + 1, z + q) - phi_sample(d, phi, x + p, y - 1, z + q));
-      n[2] += w * (phi_sample(d, phi, x + p, y + q, z + 1) - phi_sample(d, phi, x + p, y + q, z - 1));
+    for (int k = 0; k < 7; ++k) {
+      xp[k] = wrap_axis(x + k - 3, d.nx, d.per[0]);
+      yp[k] = wrap_axis(y + k - 3, d.ny, d.per[1]);
+      zp[k] = wrap_axis(z + k - 3, d.nz, d.per[2]);
+      xm[k] = mirror(xp[k], d.nx, d.per[0]);
+      ym[k] = mirror(yp[k], d.ny, d.per[1]);
+      zm[k] = mirror(zp[k], d.nz, d.per[2]);
     }
-}
+  }
+  __device__ __forceinline__ static int mirror(int c, int n, int per) {
+    if (per) return c;
+    if (c <= 0) return 1 - c;
+    if (c >= n - 1) return 2 * n - 3 - c;
+    return c;
+  }
+  __device__ __forceinline__ R get(const Dev &d, const R *phi, int ox, int oy, int oz) const {
+    const int cx = xp[ox + 3], cy = yp[oy + 3], cz = zp[oz + 3];
+    if (!d.has_walls) return phi[cx + d.nx * (cy + d.ny * cz)];
+    if (cx >= 0 && cx < d.nx && cy >= 0 && cy < d.ny && cz >= 0 && cz < d.nz) {
+      const int i = cx + d.nx * (cy + d.ny * cz);
+      if ((d.flag_src[i] & TYPE_MASK) != T_WALL) return phi[i];
+    }
+    return phi[xm[ox + 3] + d.nx * (ym[oy + 3] + d.ny * zm[oz + 3])];
+  }
+};
 
-// Height-function curvature from 7-cell columns along axis dd over a 3x3
-// footprint; kappa > 0 where the liquid is convex.
-template <class R>
-__device__ __noinline__ R height_curvature_axis(const Dev &d, const R *phi, int x, int y, int z,
-                                                int dd) {
-  const int e1 = (dd == 0) ? 1 : 0;
-  const int e2 = (dd == 2) ? 1 : 2;
+// Height-function curvature along axis DD with the 3x3x3 neighbourhood of
+// the cell already in registers (B[dz][dy][dx]); same sums, same order.
+template <int DD, class R>
+__device__ __forceinline__ R height_curvature_cached(const Dev &d, const R *phi,
+                                                     const PhiWin<R> &W, const R (&B)[3][3][3]) {
   R H[3][3];
 #pragma unroll
   for (int a = -1; a <= 1; ++a)
@@ -400,11 +427,13 @@ __device__ __noinline__ R height_curvature_axis(const Dev &d, const R *phi, int 
       R s = (R)0;
 #pragma unroll
       for (int k = -3; k <= 3; ++k) {
-        int c[3] = {x, y, z};
-        c[e1] += a;
-        c[e2] += b;
-        c[dd] += k;
-        s += phi_sample(d, phi, c[0], c[1], c[2]);
+        const int ox = DD == 0 ? k : a;
+        const int oy = DD == 0 ? a : (DD == 1 ? k : b);
+        const int oz = DD == 2 ? k : b;
+        R v;
+        if (k >= -1 && k <= 1) v = B[oz + 1][oy + 1][ox + 1];
+        else v = W.get(d, phi, ox, oy, oz);
+        s += v;
       }
       H[a + 1][b + 1] = s;
     }
@@ -419,25 +448,129 @@ __device__ __noinline__ R height_curvature_axis(const Dev &d, const R *phi, int 
   return (R)-0.5 * num / den;
 }
 
-// Mean curvature: height function along the dominant normal axis; axes
-// within the tie band of the largest |n_i| are averaged (order x, y, z).
-template <class R>
-__device__ __forceinline__ R curvature(const Dev &d, const R *phi, int x, int y, int z,
-                                       const R *n) {
-  const R an[3] = {fabs(n[0]), fabs(n[1]), fabs(n[2])};
-  R m = an[0];
-  if (an[1] > m) m = an[1];
-  if (an[2] > m) m = an[2];
-  if (m == (R)0) return (R)0;
-  const R thr = m - (R)TIE_REL * m;
-  R sum = (R)0;
-  int cnt = 0;
-  for (int dd = 0; dd < 3; ++dd)
-    if (an[dd] >= thr) {
-      sum += height_curvature_axis(d, phi, x, y, z, dd);
-      ++cnt;
+// Interface geometry of the listed interface cells: Youngs normal and
+// height-function curvature from the fill levels of time t, gas density
+// from p_V + 2 sigma kappa (Sec. 2.2) and the directions to reconstruct
+// (moving from the gas side into the liquid beyond the tie band).  Results
+// are stored by list position.
+template <class P>
+__global__ void __launch_bounds__(256) k_geom(Dev d) {
+  using R = typename P::R;
+  const R *phi = (const R *)d.phi_src;
+  const int n = d.sc->n_il_src;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const long long i = d.ilist_src[k];
+    int x, y, z;
+    coords(d, i, x, y, z);
+    const PhiWin<R> W(d, x, y, z);
+    R B[3][3][3];
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) B[dz + 1][dy + 1][dx + 1] = W.get(d, phi, dx, dy, dz);
+    R nv[3] = {(R)0, (R)0, (R)0};
+#pragma unroll
+    for (int p = -1; p <= 1; ++p)
+#pragma unroll
+      for (int q = -1; q <= 1; ++q) {
+        const R w = (R)((p == 0 ? 2 : 1) * (q == 0 ? 2 : 1));
+        nv[0] += w * (B[q + 1][p + 1][2] - B[q + 1][p + 1][0]);
+        nv[1] += w * (B[q + 1][2][p + 1] - B[q + 1][0][p + 1]);
+        nv[2] += w * (B[2][q + 1][p + 1] - B[0][q + 1][p + 1]);
+      }
+    // curvature: dominant axis, ties averaged in the order x, y, z
+    const R an[3] = {fabs(nv[0]), fabs(nv[1]), fabs(nv[2])};
+    R m = an[0];
+    if (an[1] > m) m = an[1];
+    if (an[2] > m) m = an[2];
+    R kappa = (R)0;
+    if (m != (R)0) {
+      const R thr = m - (R)TIE_REL * m;
+      R sum = (R)0;
+      int cnt = 0;
+      if (an[0] >= thr) {
+        sum += height_curvature_cached<0>(d, phi, W, B);
+        ++cnt;
+      }
+      if (an[1] >= thr) {
+        sum += height_curvature_cached<1>(d, phi, W, B);
+        ++cnt;
+      }
+      if (an[2] >= thr) {
+        sum += height_curvature_cached<2>(d, phi, W, B);
+        ++cnt;
+      }
+      kappa = sum / (R)cnt;
     }
-  return sum / (R)cnt;
+    const int slot = d.bslot[i];
+    R g;
+    if constexpr (P::EXACT) {
+      const R p_gas = (R)d.b_p[slot] + (R)2.0 * (R)d.sigma * kappa;
+      g = (R)3.0 * p_gas;  // rho_gas, p = rho cs^2
+    } else {
+      g = (R)(3.0 * d.b_p[slot] - 1.0) + (R)6 * (R)d.sigma * kappa;  // rho_gas - 1
+    }
+    const R nn = an[0] + an[1] + an[2];
+    uint32_t mask = 0;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      const R cn = CX[a] * nv[0] + CY[a] * nv[1] + CZ[a] * nv[2];
+      if (cn > (R)TIE_REL * nn) mask |= 1u << a;
+    }
+    ((R *)d.gasv)[k] = g;
+    d.nmask[k] = mask;
+  }
+}
+
+// Sum of the gas-side equilibria of direction a and its opposite, in the
+// stored representation: f_eq,a + f_eq,abar (FP64, each term in the
+// reference operation order) or (f_eq,a - w_a) + (f_eq,abar - w_abar).
+template <class P>
+__device__ __forceinline__ typename P::R gas_pair(typename P::R rho, typename P::R drho,
+                                                  const typename P::R *u, int a) {
+  using R = typename P::R;
+  if constexpr (P::EXACT) {
+    const double cs2 = 1.0 / 3.0;
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const int b = opp(a);
+    const double cua = CX[a] * u[0] + CY[a] * u[1] + CZ[a] * u[2];
+    const double cub = CX[b] * u[0] + CY[b] * u[1] + CZ[b] * u[2];
+    const double fa = rho * wgt(a) * (1.0 + cua / cs2 + (cua * cua) / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+    const double fb = rho * wgt(b) * (1.0 + cub / cs2 + (cub * cub) / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+    return fa + fb;
+  } else {
+    const R cu = (R)CX[a] * u[0] + (R)CY[a] * u[1] + (R)CZ[a] * u[2];
+    const R uu15 = (R)1.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    return (R)2 * (R)wgt(a) * (drho + rho * ((R)4.5 * cu * cu - uu15));
+  }
+}
+
+// Appends the lanes with pred set to a list; returns each such lane's slot.
+// Every lane of the wave must call it.
+__device__ __forceinline__ int wave_append(bool pred, int *counter) {
+  const unsigned long long m = __ballot(pred);
+  if (!m) return -1;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
+  base = __shfl(base, leader, 64);
+  return base + (int)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+// Claims cell j once per step (bit j of the mark field); true for the
+// first caller.
+__device__ __forceinline__ bool claim_cell(const Dev &d, long long j) {
+  const unsigned bit = 1u << (8 * (unsigned)(j & 3));
+  const unsigned old = atomicOr(&d.mark[j >> 2], bit);
+  return (old & bit) == 0;
+}
+
+__device__ __forceinline__ void release_cell(const Dev &d, long long j) {
+  const unsigned bit = 1u << (8 * (unsigned)(j & 3));
+  atomicAnd(&d.mark[j >> 2], ~bit);
 }
 
 // ---------------------------------------------------------------- k_bulk
@@ -456,9 +589,9 @@ __global__ void __launch_bounds__(256) k_bulk(Dev d) {
     const uint8_t fl = d.flag_src[i];
     const uint8_t t = fl & TYPE_MASK;
     if (t == T_LIQ) {
-      const int xs[3] = {wrap_axis(x - 1, d.nx, d.per[0]), x, wrap_axis(x + 1, d.nx, d.per[0])};
-      const int ys[3] = {wrap_axis(y - 1, d.ny, d.per[1]), y, wrap_axis(y + 1, d.ny, d.per[1])};
-      const int zs[3] = {wrap_axis(z - 1, d.nz, d.per[2]), z, wrap_axis(z + 1, d.nz, d.per[2])};
+      const int xs[3] = {wrap1(x - 1, d.nx, d.per[0]), x, wrap1(x + 1, d.nx, d.per[0])};
+      const int ys[3] = {wrap1(y - 1, d.ny, d.per[1]), y, wrap1(y + 1, d.ny, d.per[1])};
+      const int zs[3] = {wrap1(z - 1, d.nz, d.per[2]), z, wrap1(z + 1, d.nz, d.per[2])};
       R f[Q];
       if (!(fl & NEAR_WALL)) {
 #pragma unroll
@@ -467,12 +600,17 @@ __global__ void __launch_bounds__(256) k_bulk(Dev d) {
           f[a] = ld<P>(d.f_src, a, d.N, s);
         }
       } else {
+        uint8_t ts[Q];
+        R own[Q];
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
           const long long s = cidx(d, xs[1 - CX[a]], ys[1 - CY[a]], zs[1 - CZ[a]]);
-          const uint8_t ts = d.flag_src[s] & TYPE_MASK;
-          f[a] = (ts == T_WALL) ? ld<P>(d.f_src, opp(a), d.N, i) : ld<P>(d.f_src, a, d.N, s);
+          ts[a] = d.flag_src[s] & TYPE_MASK;
+          f[a] = ld<P>(d.f_src, a, d.N, s);
+          own[a] = ld<P>(d.f_src, a, d.N, i);
         }
+#pragma unroll
+        for (int a = 0; a < Q; ++a) f[a] = (ts[a] == T_WALL) ? own[opp(a)] : f[a];
       }
       R rho, u[3];
       collide<P>(d, f, rho, u);
@@ -490,80 +628,70 @@ __global__ void __launch_bounds__(256) k_bulk(Dev d) {
 
 // --------------------------------------------------------------- k_iface
 
+// One interface cell: geometry, gas-side equilibrium, pull streaming with
+// bounce-back and reconstruction, mass exchange (summed in the order of the
+// neighbour directions), collision, new fill level and conversion
+// candidates.  Returns the new mass.
 template <class P>
 __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, long long i,
-                                             uint8_t fl) {
+                                             int k, uint8_t fl, uint8_t &nf_out) {
   using R = typename P::R;
   const R *phi = (const R *)d.phi_src;
   const long long N = d.N;
+  const R g = ((const R *)d.gasv)[k];
+  const uint32_t mask = d.nmask[k];
+  const R rho_gas = P::EXACT ? g : (R)1 + g;
+  const R drho_gas = P::EXACT ? g - (R)1 : g;
+
   R fs[Q];
 #pragma unroll
   for (int a = 0; a < Q; ++a) fs[a] = ld<P>(d.f_src, a, N, i);
-
-  // interface geometry and gas-side equilibrium
-  R n[3];
-  youngs_normal(d, phi, x, y, z, n);
-  const R kappa = curvature(d, phi, x, y, z, n);
-  const int slot = d.bslot[i];
-  R rho_gas, drho_gas;
-  if constexpr (P::EXACT) {
-    const R p_gas = (R)d.b_p[slot] + (R)2.0 * (R)d.sigma * kappa;
-    rho_gas = (R)3.0 * p_gas;
-    drho_gas = rho_gas - (R)1;
-  } else {
-    // p = rho cs^2: rho_gas - 1 = (3 p_V - 1) + 6 sigma kappa
-    drho_gas = (R)(3.0 * d.b_p[slot] - 1.0) + (R)6 * (R)d.sigma * kappa;
-    rho_gas = (R)1 + drho_gas;
-  }
-  R feq_gas[Q];
+  R ub[3];
   {
-    R r, dr, ub[3];
+    R r, dr;
     recover<P>(d, fs, r, dr, ub);
-    eqv<P>(rho_gas, drho_gas, ub, feq_gas);
   }
-  const R nn = fabs(n[0]) + fabs(n[1]) + fabs(n[2]);
 
-  // pull streaming with bounce-back and reconstruction; keep the raw
-  // streamed values for the mass exchange
-  R fin[Q], raw[Q];
-  uint8_t tsrc[Q];
+  // al: direction towards the neighbour y = x + c_al, which is the source of
+  // the pulled direction a = opp(al)
+  const Nb3 nb(d, x, y, z);
+  R fin[Q];
   fin[0] = fs[0];
-  raw[0] = fs[0];
-  tsrc[0] = T_IFACE;
-#pragma unroll
-  for (int a = 1; a < Q; ++a) {
-    const int b = opp(a);
-    const long long s = nbr(d, x, y, z, -CX[a], -CY[a], -CZ[a]);
-    const uint8_t ts = d.flag_src[s] & TYPE_MASK;
-    tsrc[a] = ts;
-    const R recon = feq_gas[a] + feq_gas[b] - fs[b];
-    raw[a] = (R)0;
-    if (ts == T_WALL) {
-      fin[a] = fs[b];
-    } else if (ts == T_GAS || ts == T_INLET) {
-      fin[a] = recon;
-    } else {
-      raw[a] = ld<P>(d.f_src, a, N, s);
-      fin[a] = raw[a];
-      const R cn = CX[a] * n[0] + CY[a] * n[1] + CZ[a] * n[2];
-      if (cn > (R)TIE_REL * nn) fin[a] = recon;
-    }
-  }
-
-  // mass exchange with the neighbour y = x + c_a, whose outgoing value
-  // towards x is the raw streamed value of direction opp(a)
   R dm = (R)0;
   const R phi_x = phi[i];
+  // neighbours in three groups of six: the loads of a group (types,
+  // streamed values, fill levels; unused for gas, inlet and wall
+  // neighbours) are issued together, then the rules are applied with
+  // selects; the mass exchange is summed in direction order
 #pragma unroll
-  for (int a = 1; a < Q; ++a) {
-    const int b = opp(a);
-    const uint8_t ty = tsrc[b];
-    const R diff = (ty == T_LIQ || ty == T_IFACE) ? raw[b] - fs[a] : (R)0;
-    if (ty == T_LIQ) {
-      dm += diff;
-    } else if (ty == T_IFACE) {
-      const long long yidx = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
-      dm += (R)0.5 * (phi_x + phi[yidx]) * diff;
+  for (int g = 0; g < 3; ++g) {
+    uint8_t ts[6];
+    R raw[6], phn[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int al = 1 + 6 * g + k;
+      const long long s = nb.at(d, CX[al], CY[al], CZ[al]);
+      ts[k] = d.flag_src[s] & TYPE_MASK;
+      raw[k] = ld<P>(d.f_src, opp(al), N, s);
+      phn[k] = phi[s];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int al = 1 + 6 * g + k;
+      const int a = opp(al);
+      const R recon = gas_pair<P>(rho_gas, drho_gas, ub, a) - fs[al];
+      const uint8_t t = ts[k];
+      const bool gas_src = t == T_GAS || t == T_INLET;
+      const bool fluid_src = t == T_LIQ || t == T_IFACE;
+      R v = ((mask >> a) & 1u) ? recon : raw[k];
+      v = gas_src ? recon : v;
+      v = (t == T_WALL) ? fs[al] : v;
+      fin[a] = v;
+      // mass exchange: liquid 1, interface mean fill level, others 0
+      // (adding 0 * diff leaves the sum unchanged)
+      const R diff = fluid_src ? raw[k] - fs[al] : (R)0;
+      const R w = (t == T_IFACE) ? (R)0.5 * (phi_x + phn[k]) : (R)0;
+      dm += (t == T_LIQ) ? diff : w * diff;
     }
   }
   const R m_new = ((R *)d.mass)[i] + dm + (R)d.sc->share;
@@ -580,129 +708,144 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
   if (phi_new > (R)1 + (R)d.eps && !(fl & NEAR_INLET)) nf |= CAND_F;
   if (phi_new < -(R)d.eps) nf |= CAND_E;
   d.flag_dst[i] = nf;
+  nf_out = nf;
   return (double)m_new;
 }
 
+// Interface cells of time t (list), one per thread; conversion candidates
+// are appended to the candidate list.
 template <class P, bool WITH_MASS>
 __global__ void __launch_bounds__(256) k_iface(Dev d) {
   Fx mass;
-  const int rows = d.ny * d.nz;
-  for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-    const int y = row % d.ny, z = row / d.ny;
-    for (int x = threadIdx.x; x < d.nx; x += blockDim.x) {
-      const long long i = cidx(d, x, y, z);
-      const uint8_t fl = d.flag_src[i];
-      if ((fl & TYPE_MASK) == T_IFACE) {
-        const double m = iface_cell<P>(d, x, y, z, i, fl);
-        if (WITH_MASS) mass.add(m, FX_VOL);
-      }
+  const int n = d.sc->n_il_src;
+  for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const int k = base + threadIdx.x;
+    bool cand = false;
+    long long i = 0;
+    if (k < n) {
+      i = d.ilist_src[k];
+      int x, y, z;
+      coords(d, i, x, y, z);
+      uint8_t nf;
+      const double m = iface_cell<P>(d, x, y, z, i, k, d.flag_src[i], nf);
+      if (WITH_MASS) mass.add(m, FX_VOL);
+      cand = (nf & (CAND_F | CAND_E)) != 0;
     }
+    const int pos = wave_append(cand, &d.sc->n_cand);
+    if (cand) d.clist[pos] = (int)i;
   }
   if (WITH_MASS) block_fx_add(mass, d.mass_acc, blockIdx.x % SUB_MASS);
 }
 
-// ------------------------------------------------------------- k_convert
+// ------------------------------------------------------------- conversions
 
-// New cell types (phase-synchronous; every rule reads the candidate bits
-// and the types of time t):
-//   filled interface -> liquid; emptied interface (no filled neighbour)
-//   -> gas; gas next to a filled cell -> interface; liquid next to an
-//   emptied cell -> interface.
-// New interface cells from gas get f = f_eq(mean rho, mean u) of their
-// neighbours that were interface or liquid at t, and m = 0; those from
-// liquid get m = rho and the smallest bubble ID of their emptied
-// neighbours.
+// Candidates: filled cells -> liquid; emptied cells without a filled
+// neighbour -> gas.  Gas neighbours of filled cells and liquid neighbours
+// of emptied cells become interface (each listed once).  Every rule reads
+// the candidate bits and the types of time t (phase-synchronous).
 template <class P>
-__global__ void __launch_bounds__(256) k_convert(Dev d) {
-  using R = typename P::R;
-  const int rows = d.ny * d.nz;
-  for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-    const int y = row % d.ny, z = row / d.ny;
-    for (int x = threadIdx.x; x < d.nx; x += blockDim.x) {
-      const long long i = cidx(d, x, y, z);
-      const uint8_t t = d.flag_src[i] & TYPE_MASK;
-      if (t == T_WALL || t == T_INLET) continue;
+__global__ void __launch_bounds__(256) k_conv_types(Dev d) {
+  const int n = d.sc->n_cand;
+  for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const int k = base + threadIdx.x;
+    bool F = false, E = false;
+    int x = 0, y = 0, z = 0;
+    if (k < n) {
+      const long long i = d.clist[k];
+      coords(d, i, x, y, z);
       const uint8_t fd = d.flag_dst[i];
-      uint8_t tn = t;
-      if (t == T_IFACE) {
-        if (fd & CAND_F) {
-          tn = T_LIQ;
-        } else if (fd & CAND_E) {
-          bool nf = false;
-#pragma unroll
-          for (int a = 1; a < Q; ++a)
-            if (d.flag_dst[nbr(d, x, y, z, CX[a], CY[a], CZ[a])] & CAND_F) nf = true;
-          if (!nf) tn = T_GAS;
-        }
-      } else if (t == T_GAS) {
-        bool nf = false;
+      if (fd & CAND_F) {
+        F = true;
+      } else if (fd & CAND_E) {
+        E = true;
 #pragma unroll
         for (int a = 1; a < Q; ++a)
-          if (d.flag_dst[nbr(d, x, y, z, CX[a], CY[a], CZ[a])] & CAND_F) nf = true;
-        if (nf) {
-          tn = T_IFACE;
-          // mean density and velocity of the neighbours that were fluid at t,
-          // recovered from their post-collision values
-          R rs = (R)0, us[3] = {(R)0, (R)0, (R)0};
-          int cnt = 0;
-          for (int a = 1; a < Q; ++a) {
-            const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
-            const uint8_t tj = d.flag_src[j] & TYPE_MASK;
-            if (!(tj == T_IFACE || tj == T_LIQ)) continue;
-            R v[Q];
-#pragma unroll
-            for (int c = 0; c < Q; ++c) v[c] = ld<P>(d.f_dst, c, d.N, j);
-            R r, dr, uj[3];
-            recover<P>(d, v, r, dr, uj);
-            rs += P::EXACT ? r : dr;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) us[k] += uj[k];
-            ++cnt;
-          }
-          const R mean = rs / (R)cnt;
-          const R rb = P::EXACT ? mean : (R)1 + mean;
-          const R ub[3] = {us[0] / (R)cnt, us[1] / (R)cnt, us[2] / (R)cnt};
-          R fe[Q];
-          eqv<P>(rb, P::EXACT ? rb - (R)1 : mean, ub, fe);
-#pragma unroll
-          for (int c = 0; c < Q; ++c) st<P>(d.f_dst, c, d.N, i, fe[c]);
-          ((R *)d.rhoI)[i] = rb;
-          ((R *)d.mass)[i] = (R)0;
-          atomicAdd((unsigned long long *)&d.b_ngas[d.bslot[i]], (unsigned long long)-1ll);
-        }
-      } else if (t == T_LIQ) {
-        int best_slot = -1, best_id = INT_MAX;
-        for (int a = 1; a < Q; ++a) {
-          const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
-          if (!(d.flag_dst[j] & CAND_E)) continue;
-          // j is emptied unless one of its neighbours is filled
-          const int jx = (int)(j % d.nx), jy = (int)((j / d.nx) % d.ny),
-                    jz = (int)(j / ((long long)d.nx * d.ny));
-          bool nf = false;
-          for (int b = 1; b < Q; ++b)
-            if (d.flag_dst[nbr(d, jx, jy, jz, CX[b], CY[b], CZ[b])] & CAND_F) nf = true;
-          if (nf) continue;
-          const int s = d.bslot[j];
-          const int id = d.b_id[s];
-          if (id < best_id) {
-            best_id = id;
-            best_slot = s;
-          }
-        }
-        if (best_slot >= 0) {
-          tn = T_IFACE;
-          R v[Q];
-#pragma unroll
-          for (int c = 0; c < Q; ++c) v[c] = ld<P>(d.f_dst, c, d.N, i);
-          R r, dr, uu[3];
-          recover<P>(d, v, r, dr, uu);
-          ((R *)d.mass)[i] = r;
-          ((R *)d.rhoI)[i] = r;
-          d.bslot[i] = best_slot;
+          if (d.flag_dst[nbr(d, x, y, z, CX[a], CY[a], CZ[a])] & CAND_F) E = false;
+      }
+      if (F) d.flag_dst[i] = (uint8_t)((fd & ~TYPE_MASK) | T_LIQ);
+      if (E) d.flag_dst[i] = (uint8_t)((fd & ~TYPE_MASK) | T_GAS);
+    }
+    for (int a = 1; a < Q; ++a) {
+      bool claim = false;
+      long long j = 0;
+      if (F || E) {
+        j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
+        const uint8_t tj = d.flag_src[j] & TYPE_MASK;
+        if ((F && tj == T_GAS) || (E && tj == T_LIQ)) {
+          d.flag_dst[j] = (uint8_t)((d.flag_dst[j] & ~TYPE_MASK) | T_IFACE);
+          claim = claim_cell(d, j);
         }
       }
-      if (tn != t) d.flag_dst[i] = (uint8_t)((fd & ~TYPE_MASK) | tn);
+      const int pos = wave_append(claim, &d.sc->n_new);
+      if (claim) d.nlist[pos] = (int)j;
     }
+  }
+}
+
+// New interface cells.  From gas: f = f_eq(mean rho, mean u) of the
+// neighbours that were interface or liquid at t (recovered from their
+// post-collision values), m = 0, ID kept.  From liquid: m = rho of its own
+// post-collision values, the smallest bubble ID of its emptied neighbours.
+template <class P>
+__global__ void __launch_bounds__(256) k_conv_init(Dev d) {
+  using R = typename P::R;
+  const int n = d.sc->n_new;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const long long i = d.nlist[k];
+    int x, y, z;
+    coords(d, i, x, y, z);
+    const uint8_t t = d.flag_src[i] & TYPE_MASK;
+    if (t == T_GAS) {
+      R rs = (R)0, us[3] = {(R)0, (R)0, (R)0};
+      int cnt = 0;
+      for (int a = 1; a < Q; ++a) {
+        const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
+        const uint8_t tj = d.flag_src[j] & TYPE_MASK;
+        if (!(tj == T_IFACE || tj == T_LIQ)) continue;
+        R v[Q];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) v[c] = ld<P>(d.f_dst, c, d.N, j);
+        R r, dr, uj[3];
+        recover<P>(d, v, r, dr, uj);
+        rs += P::EXACT ? r : dr;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) us[c] += uj[c];
+        ++cnt;
+      }
+      const R mean = rs / (R)cnt;
+      const R rb = P::EXACT ? mean : (R)1 + mean;
+      const R ubar[3] = {us[0] / (R)cnt, us[1] / (R)cnt, us[2] / (R)cnt};
+      R fe[Q];
+      eqv<P>(rb, P::EXACT ? rb - (R)1 : mean, ubar, fe);
+#pragma unroll
+      for (int c = 0; c < Q; ++c) st<P>(d.f_dst, c, d.N, i, fe[c]);
+      ((R *)d.rhoI)[i] = rb;
+      ((R *)d.mass)[i] = (R)0;
+      atomicAdd((unsigned long long *)&d.b_ngas[d.bslot[i]], (unsigned long long)-1ll);
+    } else {
+      int best_slot = -1, best_id = INT_MAX;
+      for (int a = 1; a < Q; ++a) {
+        const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
+        const bool emptied = (d.flag_src[j] & TYPE_MASK) == T_IFACE &&
+                             (d.flag_dst[j] & TYPE_MASK) == T_GAS;
+        if (!emptied) continue;
+        const int s = d.bslot[j];
+        const int id = d.b_id[s];
+        if (id < best_id) {
+          best_id = id;
+          best_slot = s;
+        }
+      }
+      R v[Q];
+#pragma unroll
+      for (int c = 0; c < Q; ++c) v[c] = ld<P>(d.f_dst, c, d.N, i);
+      R r, dr, uu[3];
+      recover<P>(d, v, r, dr, uu);
+      ((R *)d.mass)[i] = r;
+      ((R *)d.rhoI)[i] = r;
+      d.bslot[i] = best_slot;
+    }
+    release_cell(d, i);
   }
 }
 
@@ -713,18 +856,13 @@ __global__ void __launch_bounds__(256) k_convert(Dev d) {
 __device__ __forceinline__ int blk_pos(int dx, int dy, int dz) {
   return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
 }
-__device__ __forceinline__ uint32_t adj_mask(int p) {
-  // block positions adjacent (18-neighbourhood) to position p
-  const int px = p % 3 - 1, py = (p / 3) % 3 - 1, pz = p / 9 - 1;
-  uint32_t m = 0;
-  for (int q = 0; q < 27; ++q) {
-    const int dx = q % 3 - 1 - px, dy = (q / 3) % 3 - 1 - py, dz = q / 9 - 1 - pz;
-    const int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy, az = dz < 0 ? -dz : dz;
-    const int l1 = ax + ay + az;
-    if (ax <= 1 && ay <= 1 && az <= 1 && l1 >= 1 && l1 <= 2) m |= 1u << q;
-  }
-  return m;
-}
+// Block positions adjacent (18-neighbourhood) to each position p.
+__constant__ uint32_t ADJ27[27] = {
+    0x000161au, 0x0002e3du, 0x0004c32u, 0x000b2d3u, 0x00175efu, 0x0026996u, 0x0019098u,
+    0x003a178u, 0x00340b0u, 0x02c340bu, 0x05c7a17u, 0x0986426u, 0x165a659u, 0x2ebdebau,
+    0x4d32d34u, 0x32130c8u, 0x742f1d0u, 0x68161a0u, 0x0681600u, 0x0f42e00u, 0x0c84c00u,
+    0x34cb200u, 0x7bd7400u, 0x65a6800u, 0x2619000u, 0x5e3a000u, 0x2c34000u};
+__device__ __forceinline__ uint32_t adj_mask(int p) { return ADJ27[p]; }
 
 // Removing the filled cell x from the gas region cannot disconnect it if
 // (a) x's gas-region neighbours (new state) are connected inside x's 3x3x3
@@ -768,48 +906,53 @@ __global__ void __launch_bounds__(256) k_excess(Dev d) {
 #pragma unroll
   for (int c = 0; c < EX_WORDS; ++c) orphan.w[c] = 0;
   bool trig = false;
-  const int rows = d.ny * d.nz;
-  for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-    const int y = row % d.ny, z = row / d.ny;
-    for (int x = threadIdx.x; x < d.nx; x += blockDim.x) {
-      const long long i = cidx(d, x, y, z);
-      const uint8_t t = d.flag_src[i] & TYPE_MASK;
-      const uint8_t tn = d.flag_dst[i] & TYPE_MASK;
-      if (t == tn) continue;
-      if (t == T_IFACE && (tn == T_LIQ || tn == T_GAS)) {
-        const bool filled = tn == T_LIQ;
-        R *mass = (R *)d.mass;
-        const R e = filled ? mass[i] - ((R *)d.rhoI)[i] : mass[i];
-        int nI = 0;
+  const int nc = d.sc->n_cand, nn = d.sc->n_new;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nc + nn; k += gridDim.x * blockDim.x) {
+    const long long i = k < nc ? d.clist[k] : d.nlist[k - nc];
+    int x, y, z;
+    coords(d, i, x, y, z);
+    const uint8_t t = d.flag_src[i] & TYPE_MASK;
+    const uint8_t tn = d.flag_dst[i] & TYPE_MASK;
+    if (t == T_IFACE && (tn == T_LIQ || tn == T_GAS)) {
+      const bool filled = tn == T_LIQ;
+      R *mass = (R *)d.mass;
+      const R e = filled ? mass[i] - ((R *)d.rhoI)[i] : mass[i];
+      int nI = 0;
 #pragma unroll
-        for (int a = 1; a < Q; ++a)
-          if ((d.flag_dst[nbr(d, x, y, z, CX[a], CY[a], CZ[a])] & TYPE_MASK) == T_IFACE) ++nI;
-        if (nI > 0) {
-          ((R *)d.excess)[i] = e / (R)nI;
-        } else {
-          ((R *)d.excess)[i] = (R)0;
-          ex_accumulate(orphan, (double)e);
-        }
-        if (filled) {
-          mass[i] = ((R *)d.rhoI)[i];
-          ((R *)d.phi_src)[i] = (R)1;
-          ((R *)d.phi_dst)[i] = (R)1;
-          if (split_possible(d, x, y, z)) trig = true;
-          d.bslot[i] = -1;
-        } else {
-          mass[i] = (R)0;
-          ((R *)d.phi_src)[i] = (R)0;
-          ((R *)d.phi_dst)[i] = (R)0;
-          atomicAdd((unsigned long long *)&d.b_ngas[d.bslot[i]], 1ull);
-        }
-      } else if (t == T_LIQ && tn == T_IFACE) {
-        // a new gas-region cell: a merge if its gas-region neighbours carry
-        // another bubble
-        const int s = d.bslot[i];
+      for (int a = 1; a < Q; ++a)
+        if ((d.flag_dst[nbr(d, x, y, z, CX[a], CY[a], CZ[a])] & TYPE_MASK) == T_IFACE) ++nI;
+      if (nI > 0) {
+        ((R *)d.excess)[i] = e / (R)nI;
+        // tag the receivers
+#pragma unroll
         for (int a = 1; a < Q; ++a) {
           const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
-          if (in_gas_region(d.flag_dst[j] & TYPE_MASK) && d.bslot[j] != s) trig = true;
+          const uint8_t fj = d.flag_dst[j];
+          if ((fj & TYPE_MASK) == T_IFACE && !(fj & GATHER)) d.flag_dst[j] = (uint8_t)(fj | GATHER);
         }
+      } else {
+        ((R *)d.excess)[i] = (R)0;
+        ex_accumulate(orphan, (double)e);
+      }
+      if (filled) {
+        mass[i] = ((R *)d.rhoI)[i];
+        ((R *)d.phi_src)[i] = (R)1;
+        ((R *)d.phi_dst)[i] = (R)1;
+        if (split_possible(d, x, y, z)) trig = true;
+        d.bslot[i] = -1;
+      } else {
+        mass[i] = (R)0;
+        ((R *)d.phi_src)[i] = (R)0;
+        ((R *)d.phi_dst)[i] = (R)0;
+        atomicAdd((unsigned long long *)&d.b_ngas[d.bslot[i]], 1ull);
+      }
+    } else if (t == T_LIQ && tn == T_IFACE) {
+      // a new gas-region cell: a merge if its gas-region neighbours carry
+      // another bubble
+      const int s = d.bslot[i];
+      for (int a = 1; a < Q; ++a) {
+        const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
+        if (in_gas_region(d.flag_dst[j] & TYPE_MASK) && d.bslot[j] != s) trig = true;
       }
     }
   }
@@ -825,28 +968,39 @@ __global__ void __launch_bounds__(256) k_excess(Dev d) {
 template <class P>
 __global__ void __launch_bounds__(256) k_gather(Dev d) {
   using R = typename P::R;
-  long long count = 0;
   const int sub = blockIdx.x % SUB;
-  const int rows = d.ny * d.nz;
-  for (int row = blockIdx.x; row < rows; row += gridDim.x) {
-    const int y = row % d.ny, z = row / d.ny;
-    for (int x0 = 0; x0 < d.nx; x0 += blockDim.x) {
-      const int x = x0 + threadIdx.x;
-      int key = -1;
-      long long v[VACC] = {0, 0, 0, 0, 0, 1};
-      if (x < d.nx) {
-        const long long i = cidx(d, x, y, z);
-        if ((d.flag_dst[i] & TYPE_MASK) == T_IFACE) {
+  const int ni = d.sc->n_il_src, nn = d.sc->n_new;
+  for (int base = blockIdx.x * blockDim.x; base < ni + nn; base += gridDim.x * blockDim.x) {
+    const int k = base + threadIdx.x;
+    int key = -1;
+    long long v[VACC] = {0, 0, 0, 0, 0, 1};
+    long long i = 0;
+    if (k < ni + nn) {
+      i = k < ni ? d.ilist_src[k] : d.nlist[k - ni];
+      const uint8_t fd = d.flag_dst[i];
+      if ((fd & TYPE_MASK) == T_IFACE) {
+        R ph;
+        if ((fd & GATHER) || k >= ni) {
+          int x, y, z;
+          coords(d, i, x, y, z);
           R add = (R)0;
           bool touched = false;
+          if (fd & GATHER) {
+            const Nb3 nb(d, x, y, z);
+            bool conv[Q];
+            R ex[Q];
 #pragma unroll
-          for (int a = 1; a < Q; ++a) {
-            const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
-            const uint8_t t0 = d.flag_src[j] & TYPE_MASK;
-            const uint8_t t1 = d.flag_dst[j] & TYPE_MASK;
-            if (t0 == T_IFACE && (t1 == T_LIQ || t1 == T_GAS)) {
-              add += ((const R *)d.excess)[j];
-              touched = true;
+            for (int a = 1; a < Q; ++a) {
+              const long long j = nb.at(d, CX[a], CY[a], CZ[a]);
+              const uint8_t t0 = d.flag_src[j] & TYPE_MASK;
+              const uint8_t t1 = d.flag_dst[j] & TYPE_MASK;
+              conv[a] = t0 == T_IFACE && (t1 == T_LIQ || t1 == T_GAS);
+              ex[a] = ((const R *)d.excess)[j];
+            }
+#pragma unroll
+            for (int a = 1; a < Q; ++a) {
+              add += conv[a] ? ex[a] : (R)0;
+              touched = touched || conv[a];
             }
           }
           R m = ((R *)d.mass)[i];
@@ -854,19 +1008,86 @@ __global__ void __launch_bounds__(256) k_gather(Dev d) {
             m += add;
             ((R *)d.mass)[i] = m;
           }
-          const R ph = m / ((const R *)d.rhoI)[i];
+          ph = m / ((const R *)d.rhoI)[i];
           ((R *)d.phi_dst)[i] = ph;
-          key = d.bslot[i];
-          const ExTerm t = ex_split(1.0 - (double)ph);
-#pragma unroll
-          for (int c = 0; c < EX_WORDS; ++c) v[c] = t.w[c];
-          ++count;
+        } else {
+          // untouched interface cell: phi = m / rho as written by k_iface
+          ph = ((const R *)d.phi_dst)[i];
         }
+        key = d.bslot[i];
+        const ExTerm t = ex_split(1.0 - (double)ph);
+#pragma unroll
+        for (int c = 0; c < EX_WORDS; ++c) v[c] = t.w[c];
       }
-      wave_add_by_key<VACC>(key, v, d.b_vacc, SUB, sub);
     }
+    wave_add_by_key<VACC>(key, v, d.b_vacc, SUB, sub);
   }
-  block_count_add(count, d.niface_acc, sub);
+}
+
+// ------------------------------------------------------ interface list
+
+// The interface cells of t+1 in increasing cell order (stream compaction
+// over tiles of LTILE cells: count, scan, fill), so that the list kernels
+// of the next step see spatially coherent cells in every wave.
+constexpr int LTILE = 4096;
+
+__global__ void __launch_bounds__(256) k_list_count(Dev d) {
+  __shared__ int part[4];
+  const long long base = (long long)blockIdx.x * LTILE;
+  int c = 0;
+  for (int k = threadIdx.x; k < LTILE; k += blockDim.x) {
+    const long long i = base + k;
+    if (i < d.N && (d.flag_dst[i] & TYPE_MASK) == T_IFACE) ++c;
+  }
+  c = (int)wave_sum((long long)c);
+  if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) d.tilecount[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+// Single block: exclusive scan of the tile counts.
+__global__ void __launch_bounds__(1024) k_list_scan(Dev d, int ntiles) {
+  __shared__ int sums[1024];
+  const int per = (ntiles + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int lo = threadIdx.x * per;
+  int t = 0;
+  for (int k = lo; k < lo + per && k < ntiles; ++k) t += d.tilecount[k];
+  sums[threadIdx.x] = t;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the per-thread totals
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int v = threadIdx.x >= (unsigned)off ? sums[threadIdx.x - off] : 0;
+    __syncthreads();
+    sums[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = sums[threadIdx.x] - t;
+  for (int k = lo; k < lo + per && k < ntiles; ++k) {
+    const int c = d.tilecount[k];
+    d.tileoff[k] = run;
+    run += c;
+  }
+  if (threadIdx.x == blockDim.x - 1) d.sc->n_il_dst = sums[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256) k_list_fill(Dev d) {
+  __shared__ int wcount[4];
+  const long long base = (long long)blockIdx.x * LTILE;
+  int run = d.tileoff[blockIdx.x];
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int k0 = 0; k0 < LTILE; k0 += blockDim.x) {
+    const long long i = base + k0 + threadIdx.x;
+    const bool pred = i < d.N && (d.flag_dst[i] & TYPE_MASK) == T_IFACE;
+    const unsigned long long m = __ballot(pred);
+    if (lane == 0) wcount[w] = (int)__popcll(m);
+    __syncthreads();
+    int before = 0;
+    for (int k = 0; k < w; ++k) before += wcount[k];
+    const int total = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    if (pred) d.ilist_dst[run + before + (int)__popcll(m & ((1ull << lane) - 1ull))] = (int)i;
+    run += total;
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------- k_volumes
@@ -875,11 +1096,27 @@ __global__ void __launch_bounds__(256) k_gather(Dev d) {
 // (1 - phi), exactly rounded; orphan bucket; total mass.
 template <class P>
 __global__ void __launch_bounds__(1024) k_volumes(Dev d) {
+  __shared__ long long red[1024 / 64][2];
+  // total mass diagnostic: block reduction of the replicated slots
+  long long mh = 0, ml = 0;
+  for (int k = threadIdx.x; k < SUB_MASS; k += blockDim.x) {
+    mh += ll(d.mass_acc[2 * k]);
+    ml += ll(d.mass_acc[2 * k + 1]);
+    d.mass_acc[2 * k] = d.mass_acc[2 * k + 1] = 0;
+  }
+  mh = wave_sum(mh);
+  ml = wave_sum(ml);
+  if (threadIdx.x % 64 == 0) {
+    red[threadIdx.x / 64][0] = mh;
+    red[threadIdx.x / 64][1] = ml;
+  }
   for (int s = threadIdx.x; s < d.max_bubbles; s += blockDim.x) {
+    if (!d.b_live[s]) continue;
     unsigned long long *acc = d.b_vacc + (long long)s * SUB * VACC;
     long long w[EX_WORDS] = {0, 0, 0, 0, 0};
     long long cnt = 0;
     for (int k = 0; k < SUB; ++k) {
+#pragma unroll
       for (int c = 0; c < EX_WORDS; ++c) {
         w[c] += ll(acc[VACC * k + c]);
         acc[VACC * k + c] = 0;
@@ -887,42 +1124,43 @@ __global__ void __launch_bounds__(1024) k_volumes(Dev d) {
       cnt += ll(acc[VACC * k + EX_WORDS]);
       acc[VACC * k + EX_WORDS] = 0;
     }
-    if (d.b_live[s]) {
-      const ExTerm g = ex_split((double)d.b_ngas[s]);
-      for (int c = 0; c < EX_WORDS; ++c) w[c] += g.w[c];
-      d.b_vol[s] = ex_value(w);
-      d.b_niface[s] = cnt;
-    }
+    const ExTerm g = ex_split((double)d.b_ngas[s]);
+#pragma unroll
+    for (int c = 0; c < EX_WORDS; ++c) w[c] += g.w[c];
+    d.b_vol[s] = ex_value(w);
+    d.b_niface[s] = cnt;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     Scalars *sc = d.sc;
-    long long nI = 0;
-    for (int k = 0; k < SUB; ++k) {
-      nI += ll(d.niface_acc[k]);
-      d.niface_acc[k] = 0;
+    long long MH = 0, ML = 0;
+    for (int k = 0; k < (int)(blockDim.x + 63) / 64; ++k) {
+      MH += red[k][0];
+      ML += red[k][1];
     }
+    const long long nI = sc->n_il_dst;
     // the bucket of the last step was spread over this step's interface
     // cells unless there were none
     const double carry = sc->n_iface > 0 ? 0.0 : sc->bucket;
-    long long bw[EX_WORDS] = {0, 0, 0, 0, 0};
+    long long bw[EX_WORDS];
     const ExTerm ct = ex_split(carry);
+#pragma unroll
     for (int c = 0; c < EX_WORDS; ++c) bw[c] = ct.w[c];
     for (int k = 0; k < SUB; ++k)
+#pragma unroll
       for (int c = 0; c < EX_WORDS; ++c) {
         bw[c] += ll(d.bucket_acc[EX_WORDS * k + c]);
         d.bucket_acc[EX_WORDS * k + c] = 0;
       }
     const double bucket = ex_value(bw);
-    long long mh = 0, ml = 0;
-    for (int k = 0; k < SUB_MASS; ++k) {
-      mh += ll(d.mass_acc[2 * k]);
-      ml += ll(d.mass_acc[2 * k + 1]);
-      d.mass_acc[2 * k] = d.mass_acc[2 * k + 1] = 0;
-    }
-    sc->total_mass = fx_value(mh, ml, FX_VOL) + carry;
+    sc->total_mass = fx_value(MH, ML, FX_VOL) + carry;
     sc->bucket = bucket;
     sc->n_iface = nI;
     sc->share = nI > 0 ? bucket / (double)nI : 0.0;
+    sc->n_il_src = sc->n_il_dst;
+    sc->n_il_dst = 0;
+    sc->n_cand = 0;
+    sc->n_new = 0;
     if (d.force_topology) sc->label_run = 1;
   }
 }
@@ -966,12 +1204,6 @@ __device__ __forceinline__ void uf_union(int32_t *lab, int a, int b) {
 #define FSLBM_GRID_STRIDE(i) \
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < d.N; \
        i += (long long)gridDim.x * blockDim.x)
-
-__device__ __forceinline__ void coords(const Dev &d, long long i, int &x, int &y, int &z) {
-  x = (int)(i % d.nx);
-  y = (int)((i / d.nx) % d.ny);
-  z = (int)(i / ((long long)d.nx * d.ny));
-}
 
 __global__ void __launch_bounds__(256) k_label_init(Dev d) {
   if (!d.sc->label_run) return;

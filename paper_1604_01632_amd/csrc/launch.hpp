@@ -5,9 +5,10 @@
 namespace fslbm {
 
 struct LaunchCfg {
-  int bx;        // threads per block of the bulk kernel (x extent)
-  int row_grid;  // blocks of the row-strided kernels
-  int cell_grid; // blocks of the cell-strided (labelling, init) kernels
+  int bx;         // threads per block of the bulk kernel (x extent)
+  int list_grid;  // blocks of the interface-list kernels
+  int small_grid; // blocks of the conversion-list kernels
+  int cell_grid;  // blocks of the cell-strided (labelling, init) kernels
   int with_mass; // accumulate the total mass in the stream-collide kernels
 };
 
