@@ -66,6 +66,60 @@ def cpu_baseline(scene, seconds: float, threads: int) -> dict:
                       f"step(s) from the initial state, {el:.1f} s wall"}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_p1_256cubed_fp32_hbm_traffic.md")
+CSRC = os.path.join(ROOT, "paper_1604_01632_amd", "csrc")
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the HIP sources of the library (sorted by name): the
+    recorded HBM traffic is valid only for the kernels it was measured on."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(precision: str, workload: str):
+    """HBM bytes per launch of the liquid-cell kernel from the two rocprofv3
+    counter passes (FETCH_SIZE, WRITE_SIZE) recorded under profiles/, scaled
+    by the copy-kernel factor recorded there; None when the file is missing,
+    is for another workload, or the kernel sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE) or (precision, workload) != ("fp32", "p1"):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib: int, reps: int) -> int:
+    """A plain device-to-device copy of known size, for scaling the HBM byte
+    counters (run under rocprofv3 --pmc)."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "reps": reps}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,11 +129,18 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16dev"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-phase-timing", action="store_true",
+                    help="time the window without per-phase events (no roofline figure)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (counter scaling) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         return 2
+
+    if args.copy_probe:
+        return copy_probe(args.copy_probe, 5)
 
     import numpy as np
     import torch
@@ -102,7 +163,7 @@ def main() -> int:
     s0 = r0["scalars"]
     b0 = dom.bubbles()
 
-    F.fslbm_set_timing(dom.handle, True)
+    F.fslbm_set_timing(dom.handle, not args.no_phase_timing)
     stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -126,7 +187,7 @@ def main() -> int:
     counts = {k: 0.5 * (c0[k] + c1[k]) for k in c0}
     bytes_bulk = bulk_bytes_per_launch(counts, store_bytes)
     bulk_avg_ms = T["bulk_ms"] / max(1, T["steps"])
-    achieved = bytes_bulk / (bulk_avg_ms * 1e-3) / 1e9
+    achieved = bytes_bulk / (bulk_avg_ms * 1e-3) / 1e9 if T["steps"] else 0.0
     phases = {k: round(T[k] / max(1, T["steps"]) * 1e3, 2) for k in
               ("bulk_ms", "iface_ms", "convert_ms", "excess_ms", "gather_ms", "label_ms",
                "bubbles_ms")}
@@ -166,7 +227,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": recorded_traffic(args.precision, args.workload),
             "bytes_per_launch": int(bytes_bulk),
             "avg_launch_us": round(bulk_avg_ms * 1e3, 2),
         },

@@ -140,7 +140,9 @@ size_t fslbm_workspace_bytes(const fslbm_params *params);
  * face layer holds a cell that is not WALL or INLET, or a WALL cell lies
  * elsewhere; a LIQUID cell touches a GAS or INLET cell (18-neighbourhood);
  * touching gas-region cells carry different IDs; an ID is not listed; an
- * interface fill level lies outside [-0.1, 1.1]; rho <= 0 on a fluid cell;
+ * interface fill level is not finite (any finite value is accepted: a
+ * checkpoint may hold levels beyond [0, 1] that convert in the next step);
+ * rho <= 0 on a fluid cell;
  * more bubbles than max_bubbles.  ENOMEM if the workspace is too small. */
 int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const double *phi,
                  const double *rho, const double *u, const int32_t *bubble_id,

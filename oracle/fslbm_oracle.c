@@ -524,8 +524,8 @@ orc *orc_create(const orc_params *p, const uint8_t *type, const double *phi, con
       goto fail;
     }
     o->type[i] = t;
-    if (t == ORC_I && !(phi[i] >= -0.1 && phi[i] <= 1.1)) {
-      snprintf(msg, sizeof msg, "cell %lld: interface fill level out of range", (long long)i);
+    if (t == ORC_I && !isfinite(phi[i])) {
+      snprintf(msg, sizeof msg, "cell %lld: interface fill level not finite", (long long)i);
       goto fail;
     }
     if ((t == ORC_I || t == ORC_L) && !(rho[i] > 0.0)) {
@@ -906,14 +906,25 @@ static int one_step(orc *o) {
 
   /* Phase B: filled interface cells (phi > 1 + eps, never next to an
    * inlet), emptied interface cells (phi < -eps); an emptied cell next to
-   * a filled one stays interface so that the layer stays closed. */
+   * a filled one stays interface so that the layer stays closed.  An
+   * interface cell that no longer separates liquid from gas is converted
+   * whatever its fill level (the closed-layer rule of Sec. 2.2 read as in
+   * the cited FSLBM of Koerner et al.): without a gas or inlet neighbour
+   * it is filled, without a liquid neighbour it is emptied; filling wins
+   * when both hold. */
   for (int64_t i = 0; i < N; ++i) {
-    int is_i = o->type[i] == ORC_I;
-    o->filled[i] = (uint8_t)(is_i && o->phi2[i] > 1.0 + eps && !any_neighbour_type(o, i, ORC_IN));
-    o->emptied0[i] = (uint8_t)(is_i && o->phi2[i] < -eps);
+    o->filled[i] = 0;
+    o->emptied0[i] = 0;
+    if (o->type[i] != ORC_I) continue;
+    int near_in = any_neighbour_type(o, i, ORC_IN);
+    int no_gas = !near_in && !any_neighbour_type(o, i, ORC_G);
+    int no_liq = !any_neighbour_type(o, i, ORC_L);
+    o->filled[i] = (uint8_t)(!near_in && (o->phi2[i] > 1.0 + eps || no_gas));
+    o->emptied0[i] = (uint8_t)(o->phi2[i] < -eps || no_liq);
   }
   for (int64_t i = 0; i < N; ++i)
-    o->emptied[i] = (uint8_t)(o->emptied0[i] && !any_neighbour_flag(o, i, o->filled));
+    o->emptied[i] = (uint8_t)(o->emptied0[i] && !o->filled[i] &&
+                              !any_neighbour_flag(o, i, o->filled));
 
   /* Phase C: new types.  Filled -> liquid, emptied -> gas, gas next to a
    * filled cell -> interface, liquid next to an emptied cell -> interface. */

@@ -320,8 +320,8 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
       snprintf(msg, sizeof msg, "cell %lld: walls only on non-periodic face layers", i);
       return fail(FSLBM_EINVAL, msg);
     }
-    if (t == T_IFACE && !(phi[i] >= -0.1 && phi[i] <= 1.1)) {
-      snprintf(msg, sizeof msg, "cell %lld: interface fill level out of range", i);
+    if (t == T_IFACE && !std::isfinite(phi[i])) {
+      snprintf(msg, sizeof msg, "cell %lld: interface fill level not finite", i);
       return fail(FSLBM_EINVAL, msg);
     }
     if ((t == T_IFACE || t == T_LIQ) && !(rho[i] > 0.0)) {

@@ -658,6 +658,7 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
   R fin[Q];
   fin[0] = fs[0];
   R dm = (R)0;
+  bool has_gas = false, has_liq = false;
   const R phi_x = phi[i];
   // neighbours in three groups of six: the loads of a group (types,
   // streamed values, fill levels; unused for gas, inlet and wall
@@ -683,6 +684,8 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
       const uint8_t t = ts[k];
       const bool gas_src = t == T_GAS || t == T_INLET;
       const bool fluid_src = t == T_LIQ || t == T_IFACE;
+      has_gas = has_gas || gas_src;
+      has_liq = has_liq || t == T_LIQ;
       R v = ((mask >> a) & 1u) ? recon : raw[k];
       v = gas_src ? recon : v;
       v = (t == T_WALL) ? fs[al] : v;
@@ -704,9 +707,12 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
   ((R *)d.mass)[i] = m_new;
   ((R *)d.rhoI)[i] = rho;
   ((R *)d.phi_dst)[i] = phi_new;
+  // conversion candidates: fill level beyond the thresholds, or the cell
+  // no longer separates liquid from gas (no gas / inlet neighbour: filled;
+  // no liquid neighbour: emptied); never filled next to an inlet
   uint8_t nf = fl & (STATIC_BITS | TYPE_MASK);
-  if (phi_new > (R)1 + (R)d.eps && !(fl & NEAR_INLET)) nf |= CAND_F;
-  if (phi_new < -(R)d.eps) nf |= CAND_E;
+  if ((phi_new > (R)1 + (R)d.eps || !has_gas) && !(fl & NEAR_INLET)) nf |= CAND_F;
+  if (phi_new < -(R)d.eps || !has_liq) nf |= CAND_E;
   d.flag_dst[i] = nf;
   nf_out = nf;
   return (double)m_new;

@@ -183,3 +183,43 @@ def test_unchanged_topology_keeps_ids(oracle_lib):
     assert b1["id"].tolist() == [0]
     assert o.scalars()["n_topology"] == 0
     assert b1["v_star"][0] == b0["v_star"][0]
+
+
+def test_lone_interface_cell_fills(oracle_lib):
+    """An interface layer with liquid on both sides and no gas neighbour no
+    longer separates liquid from gas: it is filled in the next step whatever
+    its fill level (phi = 0.5 here), its bubble vanishes, and with no
+    interface neighbour left its whole deficit m - rho = -0.5 per cell goes
+    to the bucket (fluid at rest in equilibrium: no mass exchange)."""
+    spec = ([(LIQ, 1.0, -1)] * 3 + [(IFACE, 0.5, 0)] + [(LIQ, 1.0, -1)] * 3 + [(IFACE, 0.5, 1)]
+            + [(GAS, 0.0, 1)] * 2 + [(IFACE, 0.5, 1)] + [(LIQ, 1.0, -1)] * 2)
+    sc = scenes.layers(spec, ny=3, nz=3)
+    m0 = oracle_lib.Oracle.from_scene(sc).scalars()["total_mass"]
+    o, b0, b1 = _run(oracle_lib, sc)
+    d = o.read()
+    assert np.all(d["cell_type"].reshape(3, 3, -1)[:, :, 3] == LIQ)
+    assert b0["id"].tolist() == [0, 1]
+    assert b1["id"].tolist() == [1]
+    s = o.scalars()
+    assert s["bucket"] == pytest.approx(-0.5 * 9, rel=1e-13)
+    assert s["total_mass"] == pytest.approx(m0, rel=1e-14)
+
+
+def test_interface_film_without_liquid_empties(oracle_lib):
+    """A two-cell interface film between two gas regions of one bubble has
+    no liquid neighbour: it is emptied whatever its fill level (0.4, 0.6);
+    no interface cell is left next to it, so its mass (phi rho, no exchange
+    at rest) goes to the bucket; the bubble keeps its ID."""
+    spec = ([(LIQ, 1.0, -1)] * 2 + [(IFACE, 0.5, 0)] + [(GAS, 0.0, 0)] * 2 + [(IFACE, 0.4, 0)]
+            + [(IFACE, 0.6, 0)] + [(GAS, 0.0, 0)] * 2 + [(IFACE, 0.5, 0)] + [(LIQ, 1.0, -1)] * 2)
+    sc = scenes.layers(spec, ny=3, nz=3)
+    m0 = oracle_lib.Oracle.from_scene(sc).scalars()["total_mass"]
+    o, b0, b1 = _run(oracle_lib, sc)
+    d = o.read()
+    t = d["cell_type"].reshape(3, 3, -1)
+    assert np.all(t[:, :, 5] == GAS) and np.all(t[:, :, 6] == GAS)
+    assert np.all(t[:, :, 2] == IFACE) and np.all(t[:, :, 9] == IFACE)
+    assert b1["id"].tolist() == [0]
+    s = o.scalars()
+    assert s["bucket"] == pytest.approx((0.4 + 0.6) * 9, rel=1e-13)
+    assert s["total_mass"] == pytest.approx(m0, rel=1e-14)
