@@ -2,9 +2,10 @@
 
 Default workload: 256^3 periodic box with 16 gas threads (radius 8, 0.1 R
 sinusoidal radius perturbation of wavelength 72, 1e-3 fill-level noise),
-tau = 0.55, sigma = 5e-3, FP32 storage and arithmetic.  The warm-up brings
-the threads to the Rayleigh-Plateau breakup, so the timed window contains
-bubble splits (labelling runs).
+tau = 0.55, sigma = 5e-3, FP32 storage and arithmetic.  The threads
+rupture (Rayleigh-Plateau) between steps ~1000 and ~1500 into about three
+bubbles each; the default window (1000 warm-up steps, 1000 timed steps)
+therefore contains the bubble splits and their labelling runs.
 
 Prints one JSON line (rank 0, N = 1) with the whole-step throughput in
 MLUPS, the HBM roofline of the dominant kernel (liquid-cell stream-collide)
@@ -123,8 +124,8 @@ def copy_probe(mib: int, reps: int) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1500)
-    ap.add_argument("--warmup", type=int, default=2500)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="p1")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16dev"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

@@ -45,9 +45,10 @@ bool launchers_for(int precision, Launchers &L) {
 
 enum Arr {
   A_F0, A_F1, A_FLAG0, A_FLAG1, A_PHI0, A_PHI1, A_MASS, A_RHOI, A_EXCESS, A_BSLOT, A_LAB,
-  A_AUX0, A_AUX1, A_AUX2, A_BID, A_BFLAGS, A_BLIVE, A_BRMIN, A_BRMAX, A_BKEPT, A_NEWROOTS,
+  A_AUX0, A_AUX2, A_BID, A_BFLAGS, A_BLIVE, A_BRMIN, A_BRMAX, A_BKEPT, A_BAFFECT, A_NEWROOTS,
   A_NEWSLOT, A_BVSTAR, A_BVOL, A_BP, A_BRATIO, A_BNGAS, A_BNIFACE, A_BVACC, A_CACC,
-  A_SCALARS, A_MASSACC, A_BUCKETACC, A_ILIST0, A_ILIST1, A_CLIST, A_NLIST, A_MARK, A_GASV, A_NMASK, A_TILECOUNT, A_TILEOFF, A_COUNT
+  A_SCALARS, A_MASSACC, A_BUCKETACC, A_ILIST0, A_ILIST1, A_CLIST, A_NLIST, A_MARK, A_GASV, A_NMASK, A_TILECOUNT, A_TILEOFF,
+  A_FIF, A_NFLAG, A_ISLOT, A_COUNT
 };
 
 struct Layout {
@@ -64,8 +65,8 @@ Layout make_layout(const fslbm_params &p, const Launchers &L) {
   sz[A_F0] = sz[A_F1] = (size_t)Q * N * L.store_bytes;
   sz[A_FLAG0] = sz[A_FLAG1] = N;
   sz[A_PHI0] = sz[A_PHI1] = sz[A_MASS] = sz[A_RHOI] = sz[A_EXCESS] = N * L.real_bytes;
-  sz[A_BSLOT] = sz[A_LAB] = sz[A_AUX0] = sz[A_AUX1] = sz[A_AUX2] = N * 4;
-  sz[A_BID] = sz[A_BFLAGS] = sz[A_BLIVE] = sz[A_BRMIN] = sz[A_BRMAX] = sz[A_BKEPT] =
+  sz[A_BSLOT] = sz[A_LAB] = sz[A_AUX0] = sz[A_AUX2] = N * 4;
+  sz[A_BID] = sz[A_BFLAGS] = sz[A_BLIVE] = sz[A_BRMIN] = sz[A_BRMAX] = sz[A_BKEPT] = sz[A_BAFFECT] =
       sz[A_NEWROOTS] = sz[A_NEWSLOT] = B * 4;
   sz[A_BVSTAR] = sz[A_BVOL] = sz[A_BP] = sz[A_BRATIO] = sz[A_BNGAS] = sz[A_BNIFACE] = B * 8;
   sz[A_BVACC] = B * SUB * VACC * 8;
@@ -78,6 +79,9 @@ Layout make_layout(const fslbm_params &p, const Launchers &L) {
   sz[A_GASV] = N * L.real_bytes;
   sz[A_NMASK] = N * 4;
   sz[A_TILECOUNT] = sz[A_TILEOFF] = ((N + 4095) / 4096) * 4;
+  sz[A_FIF] = (size_t)Q * N * L.store_bytes;
+  sz[A_NFLAG] = N;
+  sz[A_ISLOT] = N * 4;
   Layout lay;
   size_t o = 0;
   for (int k = 0; k < A_COUNT; ++k) {
@@ -156,7 +160,6 @@ void build_devs(Ctx &c) {
   d.bslot = at<int32_t>(ws, lay, A_BSLOT);
   d.lab = at<int32_t>(ws, lay, A_LAB);
   d.aux0 = at<int32_t>(ws, lay, A_AUX0);
-  d.aux1 = at<int32_t>(ws, lay, A_AUX1);
   d.aux2 = at<int32_t>(ws, lay, A_AUX2);
   d.b_id = at<int32_t>(ws, lay, A_BID);
   d.b_flags = at<int32_t>(ws, lay, A_BFLAGS);
@@ -164,6 +167,7 @@ void build_devs(Ctx &c) {
   d.b_rmin = at<int32_t>(ws, lay, A_BRMIN);
   d.b_rmax = at<int32_t>(ws, lay, A_BRMAX);
   d.b_kept = at<int32_t>(ws, lay, A_BKEPT);
+  d.b_affect = at<int32_t>(ws, lay, A_BAFFECT);
   d.newroots = at<int32_t>(ws, lay, A_NEWROOTS);
   d.newslot = at<int32_t>(ws, lay, A_NEWSLOT);
   d.b_vstar = at<double>(ws, lay, A_BVSTAR);
@@ -184,6 +188,9 @@ void build_devs(Ctx &c) {
   d.nmask = at<uint32_t>(ws, lay, A_NMASK);
   d.tilecount = at<int32_t>(ws, lay, A_TILECOUNT);
   d.tileoff = at<int32_t>(ws, lay, A_TILEOFF);
+  d.f_if = ws + lay.off[A_FIF];
+  d.nflag = at<uint8_t>(ws, lay, A_NFLAG);
+  d.islot = at<int32_t>(ws, lay, A_ISLOT);
   for (int s = 0; s < 2; ++s) {
     Dev e = d;
     e.f_src = ws + lay.off[s == 0 ? A_F0 : A_F1];
@@ -383,7 +390,7 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
 
   // ---- fields
   std::vector<double> phi_h(N), mass_h(N), rhoi_h(N, 0.0);
-  std::vector<int32_t> ilist;
+  std::vector<int32_t> ilist, islot(N, 0);
   long long n_iface = 0;
   long long Mw[EX_WORDS] = {0, 0, 0, 0, 0};
   auto madd = [&](double v) {
@@ -397,6 +404,7 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
       mass_h[i] = mass_init ? mass_init[i] : phi[i] * rho[i];
       rhoi_h[i] = rho[i];
       madd(mass_h[i]);
+      islot[i] = (int32_t)ilist.size();
       ilist.push_back((int32_t)i);
       ++n_iface;
     } else if (t == T_LIQ) {
@@ -448,6 +456,7 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
   UP(d.rhoI, rhoi_p.data(), rhoi_p.size());
   UP(d.bslot, bslot.data(), N * 4);
   if (!ilist.empty()) UP(d.ilist_src, ilist.data(), ilist.size() * 4);
+  UP(d.islot, islot.data(), N * 4);
   UP(d.b_id, b_id.data(), B * 4);
   UP(d.b_flags, b_flags.data(), B * 4);
   UP(d.b_live, b_live.data(), B * 4);
@@ -465,7 +474,7 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
   madd(sc.bucket);
   sc.total_mass = ex_value(Mw);
   sc.n_live = n_bubbles;
-  sc.label_run = 1;  // the first step labels the gas region
+  sc.label_run = 2;  // the first step labels the whole gas region
   sc.n_il_src = (int)n_iface;
   UP(d.sc, &sc, sizeof sc);
   // PDFs, through the destination lattice as FP64 staging

@@ -54,7 +54,7 @@ struct Scalars {
   double total_mass;
   int next_id;
   int n_live;
-  int label_run;         // labelling requested for the current step
+  int label_run;         // labelling this step: 1 marked bubbles, 2 all
   int err;               // ERR_* bits
   int nnew;              // new components of the current labelling run
   int nfree;
@@ -86,12 +86,13 @@ struct Dev {
   void *phi_src, *phi_dst;
   void *mass, *rhoI, *excess;
   int32_t *bslot;
-  int32_t *lab, *aux0, *aux1, *aux2;
+  int32_t *lab, *aux0, *aux2;
   // bubble table, indexed by slot
   int32_t *b_id, *b_flags, *b_live;
   double *b_vstar, *b_vol, *b_p, *b_ratio;
   long long *b_ngas, *b_niface;
   int32_t *b_rmin, *b_rmax, *b_kept;
+  int32_t *b_affect;            // marked by the topology trigger this step
   unsigned long long *b_vacc;   // [B][SUB][VACC]
   unsigned long long *c_acc;    // [B][NACC] per new component
   int32_t *newroots;            // [B]
@@ -106,6 +107,12 @@ struct Dev {
   uint32_t *nmask;
   // per tile of the ordered interface-list build: counts and offsets
   int32_t *tilecount, *tileoff;
+  // outputs of the interface kernel by list slot (post-collision values,
+  // new flag byte), merged into the lattice by the liquid-cell kernel, and
+  // the list slot of every interface cell of time t
+  void *f_if;
+  uint8_t *nflag;
+  int32_t *islot;
   // scalars and global accumulators
   Scalars *sc;
   unsigned long long *mass_acc;   // [SUB_MASS][2]

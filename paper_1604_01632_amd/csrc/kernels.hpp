@@ -248,11 +248,14 @@ __device__ __forceinline__ void eqv(typename P::R rho, typename P::R drho,
     feq_exact(rho, u, out);
   } else {
     const R uu15 = (R)1.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    R sum = (R)0;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
+    for (int a = 1; a < Q; ++a) {
       const R cu = (R)CX[a] * u[0] + (R)CY[a] * u[1] + (R)CZ[a] * u[2];
       out[a] = (R)wgt(a) * (drho + rho * ((R)3 * cu + (R)4.5 * cu * cu - uu15));
+      sum += out[a];
     }
+    out[0] = drho - sum;  // the deviations sum to rho - 1 (see collide)
   }
 }
 
@@ -344,11 +347,11 @@ __device__ __forceinline__ void collide(const Dev &d, typename P::R *f, typename
     const R kp = (R)1 - (R)0.5 * wp, km = (R)1 - (R)0.5 * wm;
     const R uu15 = (R)1.5 * (ux * ux + uy * uy + uz * uz);
     const R ug3 = (R)3 * (ux * gx + uy * gy + uz * gz);
-    {
-      const R w0 = (R)wgt(0);
-      const R eq0 = w0 * (dr - rho * uu15);
-      f[0] = f[0] - wp * (f[0] - eq0) - kp * w0 * rho * ug3;
-    }
+    // The rest population takes what the moving ones leave of the
+    // equilibrium (sum = rho - 1) and of the force term (sum = 0): the float
+    // weights do not sum to one, and that bias times rho - 1 (of one sign
+    // in a pressurised liquid) would otherwise drift the mass every step.
+    R sum_eq = (R)0, sum_s = (R)0;
 #pragma unroll
     for (int a = 1; a < Q; a += 2) {
       const int b = a + 1;
@@ -365,6 +368,13 @@ __device__ __forceinline__ void collide(const Dev &d, typename P::R *f, typename
       const R dodd = -wm * (fo - eq_odd) + km * s_odd;
       f[a] = f[a] + de + dodd;
       f[b] = f[b] + de - dodd;
+      sum_eq += eq_even;
+      sum_s += s_even;
+    }
+    {
+      const R eq0 = dr - (R)2 * sum_eq;
+      const R s0 = (R)-2 * sum_s;
+      f[0] = f[0] - wp * (f[0] - eq0) + kp * s0;
     }
     rho_o = rho;
     u_o[0] = ux;
@@ -575,24 +585,30 @@ __device__ __forceinline__ void release_cell(const Dev &d, long long j) {
 
 // ---------------------------------------------------------------- k_bulk
 
-// Liquid cells: pull streaming (half-way bounce-back from walls) and
-// collision.  Also copies the flag of gas / wall / inlet cells to the new
-// flag field; interface cells are left to k_iface.
+// Every cell of a row: liquid cells pull (half-way bounce-back from walls)
+// and collide; interface cells take the post-collision values and flag
+// that k_iface left at their list slot; gas, wall and inlet cells store
+// zeros (their PDFs are undefined).  Every row of the new lattice and flag
+// field is thus written whole, in one coalesced pass.
 template <class P, bool WITH_MASS>
 __global__ void __launch_bounds__(256) k_bulk(Dev d) {
   using R = typename P::R;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y, z = blockIdx.z;
   Fx mass;
-  if (x < d.nx) {
-    const long long i = cidx(d, x, y, z);
-    const uint8_t fl = d.flag_src[i];
-    const uint8_t t = fl & TYPE_MASK;
+  const bool in = x < d.nx;
+  const long long i = in ? cidx(d, x, y, z) : 0;
+  const uint8_t fl = in ? d.flag_src[i] : (uint8_t)T_GAS;
+  const uint8_t t = fl & TYPE_MASK;
+  // a wave with no liquid or interface cell leaves its rows untouched
+  const bool fluid_wave = __ballot(in && (t == T_LIQ || t == T_IFACE)) != 0ull;
+  if (in && fluid_wave) {
+    R f[Q];
+    uint8_t nfl = fl & (STATIC_BITS | TYPE_MASK);
     if (t == T_LIQ) {
       const int xs[3] = {wrap1(x - 1, d.nx, d.per[0]), x, wrap1(x + 1, d.nx, d.per[0])};
       const int ys[3] = {wrap1(y - 1, d.ny, d.per[1]), y, wrap1(y + 1, d.ny, d.per[1])};
       const int zs[3] = {wrap1(z - 1, d.nz, d.per[2]), z, wrap1(z + 1, d.nz, d.per[2])};
-      R f[Q];
       if (!(fl & NEAR_WALL)) {
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
@@ -614,13 +630,21 @@ __global__ void __launch_bounds__(256) k_bulk(Dev d) {
       }
       R rho, u[3];
       collide<P>(d, f, rho, u);
-#pragma unroll
-      for (int a = 0; a < Q; ++a) st<P>(d.f_dst, a, d.N, i, f[a]);
       if (WITH_MASS) mass.add((double)rho, FX_VOL);
-      d.flag_dst[i] = fl & (STATIC_BITS | TYPE_MASK);
-    } else if (t != T_IFACE) {
-      d.flag_dst[i] = fl & (STATIC_BITS | TYPE_MASK);
+    } else if (t == T_IFACE) {
+      const int k = d.islot[i];
+#pragma unroll
+      for (int a = 0; a < Q; ++a) f[a] = ld<P>(d.f_if, a, d.N, k);
+      nfl = d.nflag[k];
+    } else {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) f[a] = (R)0;
     }
+#pragma unroll
+    for (int a = 0; a < Q; ++a) st<P>(d.f_dst, a, d.N, i, f[a]);
+    d.flag_dst[i] = nfl;
+  } else if (in) {
+    d.flag_dst[i] = fl & (STATIC_BITS | TYPE_MASK);
   }
   if (WITH_MASS)
     block_fx_add(mass, d.mass_acc, (blockIdx.y + blockIdx.z * gridDim.y) % SUB_MASS);
@@ -702,7 +726,7 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
   R rho, u[3];
   collide<P>(d, fin, rho, u);
 #pragma unroll
-  for (int a = 0; a < Q; ++a) st<P>(d.f_dst, a, N, i, fin[a]);
+  for (int a = 0; a < Q; ++a) st<P>(d.f_if, a, N, k, fin[a]);
   const R phi_new = m_new / rho;
   ((R *)d.mass)[i] = m_new;
   ((R *)d.rhoI)[i] = rho;
@@ -713,7 +737,7 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
   uint8_t nf = fl & (STATIC_BITS | TYPE_MASK);
   if ((phi_new > (R)1 + (R)d.eps || !has_gas) && !(fl & NEAR_INLET)) nf |= CAND_F;
   if (phi_new < -(R)d.eps || !has_liq) nf |= CAND_E;
-  d.flag_dst[i] = nf;
+  d.nflag[k] = nf;
   nf_out = nf;
   return (double)m_new;
 }
@@ -944,7 +968,10 @@ __global__ void __launch_bounds__(256) k_excess(Dev d) {
         mass[i] = ((R *)d.rhoI)[i];
         ((R *)d.phi_src)[i] = (R)1;
         ((R *)d.phi_dst)[i] = (R)1;
-        if (split_possible(d, x, y, z)) trig = true;
+        if (split_possible(d, x, y, z)) {
+          trig = true;
+          atomicOr(&d.b_affect[d.bslot[i]], 1);
+        }
         d.bslot[i] = -1;
       } else {
         mass[i] = (R)0;
@@ -958,11 +985,15 @@ __global__ void __launch_bounds__(256) k_excess(Dev d) {
       const int s = d.bslot[i];
       for (int a = 1; a < Q; ++a) {
         const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
-        if (in_gas_region(d.flag_dst[j] & TYPE_MASK) && d.bslot[j] != s) trig = true;
+        if (in_gas_region(d.flag_dst[j] & TYPE_MASK) && d.bslot[j] != s) {
+          trig = true;
+          atomicOr(&d.b_affect[s], 1);
+          atomicOr(&d.b_affect[d.bslot[j]], 1);
+        }
       }
     }
   }
-  if (trig) d.sc->label_run = 1;
+  if (trig) atomicMax(&d.sc->label_run, 1);
   block_ex_add(orphan, d.bucket_acc, blockIdx.x % SUB);
 }
 
@@ -1090,7 +1121,11 @@ __global__ void __launch_bounds__(256) k_list_fill(Dev d) {
     int before = 0;
     for (int k = 0; k < w; ++k) before += wcount[k];
     const int total = wcount[0] + wcount[1] + wcount[2] + wcount[3];
-    if (pred) d.ilist_dst[run + before + (int)__popcll(m & ((1ull << lane) - 1ull))] = (int)i;
+    if (pred) {
+      const int pos = run + before + (int)__popcll(m & ((1ull << lane) - 1ull));
+      d.ilist_dst[pos] = (int)i;
+      d.islot[i] = pos;
+    }
     run += total;
     __syncthreads();
   }
@@ -1167,7 +1202,7 @@ __global__ void __launch_bounds__(1024) k_volumes(Dev d) {
     sc->n_il_dst = 0;
     sc->n_cand = 0;
     sc->n_new = 0;
-    if (d.force_topology) sc->label_run = 1;
+    if (d.force_topology) sc->label_run = 2;
   }
 }
 
@@ -1175,16 +1210,27 @@ __global__ void __launch_bounds__(1024) k_volumes(Dev d) {
 
 // Union-find over the gas region (gas, interface, inlet cells of the new
 // state) with 18-neighbour adjacency; every root is the smallest index of
-// its component.  Roots only ever point to smaller indices, so every find
-// terminates.
+// its component.  Labels only ever decrease and always point to a cell of
+// the same component, so every find terminates.
+//
+// Only the bubbles marked by the topology trigger take part (all bubbles
+// on the first step and when labelling is forced): a bubble the trigger did
+// not mark has lost no cell and touched no other bubble, so it is still one
+// component holding no other bubble and keeps its ID.
 __device__ __forceinline__ int lab_load(const int32_t *lab, long long i) {
   return __hip_atomic_load(&lab[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Find with path halving: every visited cell is re-pointed to its
+// grandparent (an ancestor, so the tree stays valid under concurrent
+// linking), which keeps the trees shallow.
 __device__ __forceinline__ int uf_find(int32_t *lab, int i) {
   int p = lab_load(lab, i);
   while (p != i) {
-    i = p;
+    const int gp = lab_load(lab, p);
+    if (gp == p) return p;
+    atomicMin(&lab[i], gp);
+    i = gp;
     p = lab_load(lab, i);
   }
   return i;
@@ -1211,19 +1257,23 @@ __device__ __forceinline__ void uf_union(int32_t *lab, int a, int b) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < d.N; \
        i += (long long)gridDim.x * blockDim.x)
 
+// aux2 flags of a root: 1 holds an inlet cell, 2 new component, 4 holds
+// cells of more than one bubble.
 __global__ void __launch_bounds__(256) k_label_init(Dev d) {
-  if (!d.sc->label_run) return;
+  const int run = d.sc->label_run;
+  if (!run) return;
+  const bool all = run >= 2;
   FSLBM_GRID_STRIDE(i) {
-    d.lab[i] = in_gas_region(d.flag_dst[i] & TYPE_MASK) ? (int)i : -1;
-    d.aux0[i] = INT_MAX;
-    d.aux1[i] = -1;
-    d.aux2[i] = 0;
+    const bool in = in_gas_region(d.flag_dst[i] & TYPE_MASK) && (all || d.b_affect[d.bslot[i]]);
+    d.lab[i] = in ? (int)i : -1;
+    if (in) d.aux2[i] = 0;
   }
   const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (long long t = t0; t < d.max_bubbles; t += (long long)gridDim.x * blockDim.x) {
     d.b_rmin[t] = INT_MAX;
     d.b_rmax[t] = -1;
-    d.b_kept[t] = 0;
+    // bubbles outside the labelled set keep their entry
+    d.b_kept[t] = (!all && d.b_live[t] && !d.b_affect[t]) ? 1 : 0;
     for (int k = 0; k < NACC; ++k) d.c_acc[t * NACC + k] = 0;
   }
   if (t0 == 0) d.sc->nnew = 0;
@@ -1238,24 +1288,46 @@ __global__ void __launch_bounds__(256) k_label_union(Dev d) {
     // one direction of every opposite pair covers every edge once
     for (int a = 1; a < Q; a += 2) {
       const long long j = nbr_checked(d, x, y, z, CX[a], CY[a], CZ[a]);
-      if (j < 0) continue;
-      if (in_gas_region(d.flag_dst[j] & TYPE_MASK)) uf_union(d.lab, (int)i, (int)j);
+      if (j < 0 || d.lab[j] < 0) continue;
+      uf_union(d.lab, (int)i, (int)j);
     }
   }
 }
 
+// Final roots (the trees no longer change: plain loads).  Every root
+// registers itself with its bubble; an edge between cells of two bubbles
+// marks the component as mixed and registers it with both bubbles, so that
+// every bubble knows the smallest and largest root of the components that
+// hold its cells.
 __global__ void __launch_bounds__(256) k_label_roots(Dev d) {
   if (!d.sc->label_run) return;
   FSLBM_GRID_STRIDE(i) {
     if (d.lab[i] < 0) continue;
-    const int r = uf_find(d.lab, (int)i);
+    int r = (int)i, p = d.lab[i];
+    while (p != r) {
+      r = p;
+      p = d.lab[r];
+    }
     d.lab[i] = r;
     const int s = d.bslot[i];
-    atomicMin(&d.aux0[r], s);
-    atomicMax(&d.aux1[r], s);
-    atomicMin(&d.b_rmin[s], r);
-    atomicMax(&d.b_rmax[s], r);
+    if (r == (int)i) {
+      atomicMin(&d.b_rmin[s], r);
+      atomicMax(&d.b_rmax[s], r);
+    }
     if ((d.flag_dst[i] & TYPE_MASK) == T_INLET) atomicOr(&d.aux2[r], 1);
+    int x, y, z;
+    coords(d, i, x, y, z);
+    for (int a = 1; a < Q; a += 2) {
+      const long long j = nbr_checked(d, x, y, z, CX[a], CY[a], CZ[a]);
+      if (j < 0 || d.lab[j] < 0) continue;
+      const int sj = d.bslot[j];
+      if (sj == s) continue;
+      atomicOr(&d.aux2[r], 4);
+      atomicMin(&d.b_rmin[s], r);
+      atomicMax(&d.b_rmax[s], r);
+      atomicMin(&d.b_rmin[sj], r);
+      atomicMax(&d.b_rmax[sj], r);
+    }
   }
 }
 
@@ -1265,8 +1337,8 @@ __global__ void __launch_bounds__(256) k_label_decide(Dev d) {
   if (!d.sc->label_run) return;
   FSLBM_GRID_STRIDE(i) {
     if (d.lab[i] != (int)i) continue;
-    const int s = d.aux0[i];
-    const bool single = d.aux0[i] == d.aux1[i] && d.b_rmin[s] == (int)i && d.b_rmax[s] == (int)i;
+    const int s = d.bslot[i];
+    const bool single = !(d.aux2[i] & 4) && d.b_rmin[s] == (int)i && d.b_rmax[s] == (int)i;
     if (single) {
       d.b_kept[s] = 1;
     } else {
@@ -1408,6 +1480,7 @@ __global__ void __launch_bounds__(1024) k_bubbles(Dev d) {
   if (threadIdx.x == 0) live = 0;
   __syncthreads();
   for (int s = threadIdx.x; s < d.max_bubbles; s += blockDim.x) {
+    d.b_affect[s] = 0;
     if (!d.b_live[s]) continue;
     if (d.b_flags[s] & 1) d.b_vstar[s] += d.inject;
     const double v = d.b_vol[s] > 1e-2 ? d.b_vol[s] : 1e-2;

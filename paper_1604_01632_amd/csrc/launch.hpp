@@ -13,7 +13,7 @@ struct LaunchCfg {
 };
 
 // Phases of one step, in order; the host may record events between them.
-enum Phase { PH_BULK = 0, PH_IFACE, PH_CONVERT, PH_EXCESS, PH_GATHER, PH_LABEL, PH_BUBBLES, PH_COUNT };
+enum Phase { PH_IFACE = 0, PH_BULK, PH_CONVERT, PH_EXCESS, PH_GATHER, PH_LABEL, PH_BUBBLES, PH_COUNT };
 
 struct Launchers {
   void (*phase)(int ph, const Dev &d, const LaunchCfg &c, hipStream_t s);
