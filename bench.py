@@ -32,11 +32,16 @@ def log(*a):
 
 
 def bulk_bytes_per_launch(counts: dict, store_bytes: int) -> float:
-    """Algorithmic bytes of one launch of the liquid-cell kernel: every
-    liquid cell pulls 19 PDFs and writes 19 PDFs and reads and writes its
-    flag byte; gas, wall and inlet cells copy their flag byte (1 + 1 B);
-    interface cells only have their flag read (1 B)."""
-    return (counts["liq"] * (2 * 19 * store_bytes + 2) + counts["other"] * 2 + counts["iface"] * 1)
+    """Algorithmic bytes of one launch of the stream-collide kernel, which
+    writes every row of the new lattice whole: a liquid cell pulls 19 PDFs,
+    writes 19 PDFs and reads and writes its flag byte (38 S + 2); an
+    interface cell reads its flag and list slot (1 + 4), copies the 19
+    post-collision values and the new flag left at its slot into the
+    lattice (38 S + 2); a gas, wall or inlet cell reads and writes its flag
+    byte (2).  The zeros stored for gas cells next to fluid cells (a layout
+    choice that keeps cache lines whole) are not counted."""
+    S = store_bytes
+    return counts["liq"] * (38 * S + 2) + counts["iface"] * (38 * S + 7) + counts["other"] * 2
 
 
 def count_types(t) -> dict:

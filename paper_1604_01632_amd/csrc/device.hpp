@@ -62,6 +62,8 @@ struct Scalars {
   int n_il_dst;          // interface cells of t+1 appended so far
   int n_cand;            // conversion candidates of the current step
   int n_new;             // new interface cells of the current step
+  int n_lab;             // cells in the labelled set (listed in clist)
+  int pad_;
 };
 constexpr int ERR_CAPACITY = 1;
 constexpr int ERR_NONFINITE = 2;

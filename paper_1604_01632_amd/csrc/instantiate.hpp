@@ -10,10 +10,10 @@ template <class P>
 static void phase_impl(int ph, const Dev &d, const LaunchCfg &c, hipStream_t s) {
   switch (ph) {
     case PH_BULK: {
-      const dim3 bb(c.bx);
-      const dim3 gb((d.nx + c.bx - 1) / c.bx, d.ny, d.nz);
-      if (c.with_mass) k_bulk<P, true><<<gb, bb, 0, s>>>(d);
-      else k_bulk<P, false><<<gb, bb, 0, s>>>(d);
+      const int gx = (d.nx + c.bx - 1) / c.bx;
+      const unsigned nb = (unsigned)gx * (unsigned)d.ny * (unsigned)d.nz;
+      if (c.with_mass) k_bulk<P, true><<<nb, c.bx, 0, s>>>(d, gx);
+      else k_bulk<P, false><<<nb, c.bx, 0, s>>>(d, gx);
       break;
     }
     case PH_IFACE:

@@ -590,11 +590,35 @@ __device__ __forceinline__ void release_cell(const Dev &d, long long j) {
 // that k_iface left at their list slot; gas, wall and inlet cells store
 // zeros (their PDFs are undefined).  Every row of the new lattice and flag
 // field is thus written whole, in one coalesced pass.
+// Row of the grid handled by hardware block b of a 1-D launch of
+// gx * ny * nz blocks (gx blocks per row).  Blocks are dealt to the 8 XCDs
+// round-robin; block b is renumbered so that each XCD gets one contiguous
+// range of the row order below, and the row order walks the box in y-tiles
+// of ceil(ny / 8) rows, z-major inside a tile: the rows y +- 1 and z +- 1
+// that a row pulls from were then fetched by the same XCD shortly before
+// and are still in its L2.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ void bulk_row(const Dev &d, int gx, int b, int &xb, int &y, int &z) {
+  const int nb = gx * d.ny * d.nz;
+  const int k = b % N_XCD, j = b / N_XCD;
+  const int L = k * (nb / N_XCD) + min(k, nb % N_XCD) + j;
+  const int yt = (d.ny + N_XCD - 1) / N_XCD;
+  const int full = d.nz * yt * gx;  // blocks of one full y-tile
+  const int t = L / full;
+  const int r = L - t * full;
+  const int rows = min(yt, d.ny - t * yt);
+  z = r / (rows * gx);
+  const int r2 = r - z * rows * gx;
+  y = t * yt + r2 / gx;
+  xb = r2 % gx;
+}
+
 template <class P, bool WITH_MASS>
-__global__ void __launch_bounds__(256) k_bulk(Dev d) {
+__global__ void __launch_bounds__(256) k_bulk(Dev d, int gx) {
   using R = typename P::R;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y, z = blockIdx.z;
+  int xb, y, z;
+  bulk_row(d, gx, (int)blockIdx.x, xb, y, z);
+  const int x = xb * blockDim.x + threadIdx.x;
   Fx mass;
   const bool in = x < d.nx;
   const long long i = in ? cidx(d, x, y, z) : 0;
@@ -646,8 +670,7 @@ __global__ void __launch_bounds__(256) k_bulk(Dev d) {
   } else if (in) {
     d.flag_dst[i] = fl & (STATIC_BITS | TYPE_MASK);
   }
-  if (WITH_MASS)
-    block_fx_add(mass, d.mass_acc, (blockIdx.y + blockIdx.z * gridDim.y) % SUB_MASS);
+  if (WITH_MASS) block_fx_add(mass, d.mass_acc, (int)(blockIdx.x % SUB_MASS));
 }
 
 // --------------------------------------------------------------- k_iface
@@ -1202,6 +1225,7 @@ __global__ void __launch_bounds__(1024) k_volumes(Dev d) {
     sc->n_il_dst = 0;
     sc->n_cand = 0;
     sc->n_new = 0;
+    sc->n_lab = 0;
     if (d.force_topology) sc->label_run = 2;
   }
 }
@@ -1257,16 +1281,31 @@ __device__ __forceinline__ void uf_union(int32_t *lab, int a, int b) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < d.N; \
        i += (long long)gridDim.x * blockDim.x)
 
+// The cells of the labelled set, listed by k_label_init in the candidate
+// list (free once the conversions of the step are done); one cell per
+// thread in the later passes, whatever the shape of the gas region.
+#define FSLBM_LABEL_SET(i) \
+  for (int k_ = blockIdx.x * blockDim.x + threadIdx.x, n_ = d.sc->n_lab; k_ < n_; \
+       k_ += gridDim.x * blockDim.x) \
+    if (const long long i = d.clist[k_]; true)
+
 // aux2 flags of a root: 1 holds an inlet cell, 2 new component, 4 holds
 // cells of more than one bubble.
 __global__ void __launch_bounds__(256) k_label_init(Dev d) {
   const int run = d.sc->label_run;
   if (!run) return;
   const bool all = run >= 2;
-  FSLBM_GRID_STRIDE(i) {
-    const bool in = in_gas_region(d.flag_dst[i] & TYPE_MASK) && (all || d.b_affect[d.bslot[i]]);
-    d.lab[i] = in ? (int)i : -1;
-    if (in) d.aux2[i] = 0;
+  for (long long base = (long long)blockIdx.x * blockDim.x; base < d.N;
+       base += (long long)gridDim.x * blockDim.x) {
+    const long long i = base + threadIdx.x;
+    bool in = false;
+    if (i < d.N) {
+      in = in_gas_region(d.flag_dst[i] & TYPE_MASK) && (all || d.b_affect[d.bslot[i]]);
+      d.lab[i] = in ? (int)i : -1;
+      if (in) d.aux2[i] = 0;
+    }
+    const int pos = wave_append(in, &d.sc->n_lab);
+    if (in) d.clist[pos] = (int)i;
   }
   const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (long long t = t0; t < d.max_bubbles; t += (long long)gridDim.x * blockDim.x) {
@@ -1281,8 +1320,7 @@ __global__ void __launch_bounds__(256) k_label_init(Dev d) {
 
 __global__ void __launch_bounds__(256) k_label_union(Dev d) {
   if (!d.sc->label_run) return;
-  FSLBM_GRID_STRIDE(i) {
-    if (d.lab[i] < 0) continue;
+  FSLBM_LABEL_SET(i) {
     int x, y, z;
     coords(d, i, x, y, z);
     // one direction of every opposite pair covers every edge once
@@ -1301,8 +1339,7 @@ __global__ void __launch_bounds__(256) k_label_union(Dev d) {
 // hold its cells.
 __global__ void __launch_bounds__(256) k_label_roots(Dev d) {
   if (!d.sc->label_run) return;
-  FSLBM_GRID_STRIDE(i) {
-    if (d.lab[i] < 0) continue;
+  FSLBM_LABEL_SET(i) {
     int r = (int)i, p = d.lab[i];
     while (p != r) {
       r = p;
@@ -1335,7 +1372,7 @@ __global__ void __launch_bounds__(256) k_label_roots(Dev d) {
 // bubble lies in no other component; every other component is new.
 __global__ void __launch_bounds__(256) k_label_decide(Dev d) {
   if (!d.sc->label_run) return;
-  FSLBM_GRID_STRIDE(i) {
+  FSLBM_LABEL_SET(i) {
     if (d.lab[i] != (int)i) continue;
     const int s = d.bslot[i];
     const bool single = !(d.aux2[i] & 4) && d.b_rmin[s] == (int)i && d.b_rmax[s] == (int)i;
@@ -1399,14 +1436,15 @@ __global__ void __launch_bounds__(256) k_label_accumulate(Dev d) {
   using R = typename P::R;
   const Scalars *sc = d.sc;
   if (!sc->label_run || sc->nnew > d.max_bubbles || sc->nfree < sc->nnew) return;
-  for (long long base = (long long)blockIdx.x * blockDim.x; base < d.N;
-       base += (long long)gridDim.x * blockDim.x) {
-    const long long i = base + threadIdx.x;
+  const int n = sc->n_lab;
+  for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const int k = base + threadIdx.x;
     int key = -1;
     long long v[NACC];
 #pragma unroll
     for (int c = 0; c < NACC; ++c) v[c] = 0;
-    if (i < d.N && d.lab[i] >= 0) {
+    if (k < n) {
+      const long long i = d.clist[k];
       const int r = d.lab[i];
       if (d.aux2[r] & 2) {
         key = d.aux0[r];
@@ -1465,9 +1503,9 @@ __global__ void __launch_bounds__(1024) k_label_finish(Dev d) {
 __global__ void __launch_bounds__(256) k_label_rewrite(Dev d) {
   const Scalars *sc = d.sc;
   if (!sc->label_run || sc->nnew > d.max_bubbles || sc->nfree < sc->nnew) return;
-  FSLBM_GRID_STRIDE(i) {
+  FSLBM_LABEL_SET(i) {
     const int r = d.lab[i];
-    if (r >= 0 && (d.aux2[r] & 2)) d.bslot[i] = d.newslot[d.aux0[r]];
+    if (d.aux2[r] & 2) d.bslot[i] = d.newslot[d.aux0[r]];
   }
 }
 

@@ -63,6 +63,29 @@ def test_merge_split_vanish_hand_cases():
     assert o.bubbles()["id"].tolist() == [1]
 
 
+@pytest.mark.parametrize("phi", [0.5, -0.05])
+def test_lone_interface_rules(phi):
+    """Interface cells that no longer separate liquid from gas: a lone layer
+    inside the liquid fills (also below -eps), a single lone cell fills
+    without turning its liquid neighbours, a liquid-free film empties; the
+    bucket they feed is spread in the next steps."""
+    lone = ([(LIQ, 1.0, -1)] * 3 + [(IFACE, phi, 0)] + [(LIQ, 1.0, -1)] * 3 + [(IFACE, 0.5, 1)]
+            + [(GAS, 0.0, 1)] * 2 + [(IFACE, 0.5, 1)] + [(LIQ, 1.0, -1)] * 2)
+    run_pair(scenes.layers(lone, ny=3, nz=3), 4, 1, f"lone-layer-{phi}")
+    film = ([(LIQ, 1.0, -1)] * 2 + [(IFACE, 0.5, 0)] + [(GAS, 0.0, 0)] * 2 + [(IFACE, 0.4, 0)]
+            + [(IFACE, 0.6, 0)] + [(GAS, 0.0, 0)] * 2 + [(IFACE, 0.5, 0)] + [(LIQ, 1.0, -1)] * 2)
+    run_pair(scenes.layers(film, ny=3, nz=3), 4, 1, "film")
+    spec = ([(LIQ, 1.0, -1)] * 8 + [(IFACE, 0.5, 1)] + [(GAS, 0.0, 1)] * 2 + [(IFACE, 0.5, 1)]
+            + [(LIQ, 1.0, -1)] * 2)
+    sc = scenes.layers(spec, ny=5, nz=5)
+    i = 3 + len(spec) * (2 + 5 * 2)
+    sc.cell_type[i] = IFACE
+    sc.phi[i] = phi
+    sc.bubble_id[i] = 0
+    sc.bubbles.insert(0, (0, 0, -1.0, P0))
+    run_pair(sc, 4, 1, f"lone-cell-{phi}")
+
+
 def test_orifice_injection():
     sc = scenes.orifice(n=(16, 16, 20), r=3.0, g=1e-5, Q=0.05)
     run_pair(sc, 40, 10, "orifice")

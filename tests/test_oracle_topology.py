@@ -185,24 +185,39 @@ def test_unchanged_topology_keeps_ids(oracle_lib):
     assert b1["v_star"][0] == b0["v_star"][0]
 
 
-def test_lone_interface_cell_fills(oracle_lib):
+@pytest.mark.parametrize("phi", [0.5, -0.05])
+def test_lone_interface_cell_fills(oracle_lib, phi):
     """An interface layer with liquid on both sides and no gas neighbour no
     longer separates liquid from gas: it is filled in the next step whatever
-    its fill level (phi = 0.5 here), its bubble vanishes, and with no
-    interface neighbour left its whole deficit m - rho = -0.5 per cell goes
-    to the bucket (fluid at rest in equilibrium: no mass exchange)."""
-    spec = ([(LIQ, 1.0, -1)] * 3 + [(IFACE, 0.5, 0)] + [(LIQ, 1.0, -1)] * 3 + [(IFACE, 0.5, 1)]
+    its fill level (also below -eps, where filling wins over emptying and
+    its liquid neighbours stay liquid), its bubble vanishes, and with no
+    interface neighbour left its whole deficit m - rho = phi - 1 per cell
+    goes to the bucket (fluid at rest in equilibrium: no mass exchange).
+    The next step spreads the bucket evenly over the remaining interface
+    cells and empties it."""
+    spec = ([(LIQ, 1.0, -1)] * 3 + [(IFACE, phi, 0)] + [(LIQ, 1.0, -1)] * 3 + [(IFACE, 0.5, 1)]
             + [(GAS, 0.0, 1)] * 2 + [(IFACE, 0.5, 1)] + [(LIQ, 1.0, -1)] * 2)
     sc = scenes.layers(spec, ny=3, nz=3)
     m0 = oracle_lib.Oracle.from_scene(sc).scalars()["total_mass"]
     o, b0, b1 = _run(oracle_lib, sc)
     d = o.read()
-    assert np.all(d["cell_type"].reshape(3, 3, -1)[:, :, 3] == LIQ)
+    t = d["cell_type"].reshape(3, 3, -1)
+    assert np.all(t[:, :, 2:5] == LIQ)
     assert b0["id"].tolist() == [0, 1]
     assert b1["id"].tolist() == [1]
     s = o.scalars()
-    assert s["bucket"] == pytest.approx(-0.5 * 9, rel=1e-13)
+    assert s["bucket"] == pytest.approx((phi - 1.0) * 9, rel=1e-13)
     assert s["total_mass"] == pytest.approx(m0, rel=1e-14)
+    share = (phi - 1.0) * 9 / 18
+    phi_before = d["phi"].reshape(3, 3, -1)[:, :, 7].copy()
+    o.step(1)
+    s = o.scalars()
+    assert s["total_mass"] == pytest.approx(m0, rel=1e-14)
+    if phi > 0:  # a share of -0.25 leaves the remaining cells interface
+        assert s["bucket"] == 0.0
+        d = o.read()
+        assert np.all(d["cell_type"].reshape(3, 3, -1)[:, :, 7] == IFACE)
+        assert np.allclose(d["phi"].reshape(3, 3, -1)[:, :, 7], phi_before + share, atol=1e-3)
 
 
 def test_interface_film_without_liquid_empties(oracle_lib):
@@ -222,4 +237,30 @@ def test_interface_film_without_liquid_empties(oracle_lib):
     assert b1["id"].tolist() == [0]
     s = o.scalars()
     assert s["bucket"] == pytest.approx((0.4 + 0.6) * 9, rel=1e-13)
+    assert s["total_mass"] == pytest.approx(m0, rel=1e-14)
+
+
+def test_single_lone_cell_below_threshold_fills(oracle_lib):
+    """One interface cell inside the liquid, its own bubble, fill level
+    below -eps: it has no gas neighbour, so it is filled (filling wins over
+    emptying) and none of its liquid neighbours turns interface; its deficit
+    phi - 1 goes to the bucket and its bubble vanishes."""
+    spec = ([(LIQ, 1.0, -1)] * 8 + [(IFACE, 0.5, 1)] + [(GAS, 0.0, 1)] * 2 + [(IFACE, 0.5, 1)]
+            + [(LIQ, 1.0, -1)] * 2)
+    sc = scenes.layers(spec, ny=5, nz=5)
+    nx = len(spec)
+    i = 3 + nx * (2 + 5 * 2)
+    sc.cell_type[i] = IFACE
+    sc.phi[i] = -0.05
+    sc.bubble_id[i] = 0
+    sc.bubbles.insert(0, (0, 0, -1.0, P0))
+    m0 = oracle_lib.Oracle.from_scene(sc).scalars()["total_mass"]
+    o, b0, b1 = _run(oracle_lib, sc)
+    d = o.read()
+    t = d["cell_type"].reshape(5, 5, -1)
+    assert np.all(t[:, :, :8] == LIQ)
+    assert b0["id"].tolist() == [0, 1]
+    assert b1["id"].tolist() == [1]
+    s = o.scalars()
+    assert s["bucket"] == pytest.approx(-1.05, rel=1e-13)
     assert s["total_mass"] == pytest.approx(m0, rel=1e-14)
