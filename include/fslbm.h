@@ -190,6 +190,61 @@ int fslbm_destroy(void *handle);
 /* Message of the calling thread's last failure ("" if none). */
 const char *fslbm_last_error(void);
 
+/* ---------------------------------------------------------------------
+ * Batched form: many independent domains (uneven sizes, each created with
+ * fslbm_create, all of one precision) advanced together.  Every kernel of
+ * a step is launched once for all domains (each block finds its domain
+ * from per-kernel block-offset tables), and one whole step of all domains
+ * is captured in a HIP graph at creation, so that a batch step is one
+ * graph launch.  Each domain computes exactly what fslbm_step computes for
+ * it alone (bit for bit).
+ *
+ * Autotuning at creation: the stream-collide block size (128 or 256
+ * threads) and the order of domains in the block map (as given, or by
+ * decreasing size) are chosen by timing the stream-collide kernel of the
+ * batch on the live state (a probe without the mass accumulator that only
+ * writes buffers the next step rewrites).  The choice is appended to the
+ * text file tuning_cache_path (may be NULL) under a key made of the
+ * precision and the domain extents, and read from it next time.
+ * --------------------------------------------------------------------- */
+
+/* Device bytes of the batch tables for n_domains (0 if n_domains < 1). */
+size_t fslbm_batch_workspace_bytes(int32_t n_domains);
+
+typedef struct {
+  int32_t bulk_threads;  /* chosen stream-collide block size */
+  int32_t order;         /* 0: domains as given, 1: by decreasing size */
+  int32_t from_cache;    /* 1 if the choice came from the tuning cache */
+  int32_t pad;
+  int64_t cells;         /* cells of all domains */
+  float probe_ms[4];     /* probe times of (256, given), (256, size), (128, given), (128, size) */
+} fslbm_batch_info;
+
+/* Build a batch over handles[n] (distinct, same precision).  The device
+ * workspace (>= fslbm_batch_workspace_bytes(n), 256-byte aligned) holds
+ * the tables and belongs to the caller; it and the handles must outlive the
+ * batch.  stream: the caller's hipStream_t (NULL = default); batch steps
+ * are ordered after work already queued on it and on the domains' own
+ * streams, and before work queued there afterwards.  The batch runs on a
+ * stream of its own (default priority).  Stepping a member domain on its
+ * own between batch steps is allowed (the batch then rebuilds its tables).
+ * EINVAL on NULL or repeated handles or mixed precisions, ENOMEM if the
+ * workspace is too small, EDEVICE on HIP failures. */
+int fslbm_batch_create(void *const *handles, int32_t n, const char *tuning_cache_path,
+                       void *device_workspace, size_t workspace_bytes, void *stream,
+                       void **out_batch);
+
+/* Enqueue n_steps >= 0 steps of every domain of the batch (n_steps graph
+ * launches).  Asynchronous errors of a domain are reported by fslbm_sync,
+ * fslbm_read_fields or fslbm_bubbles on its handle. */
+int fslbm_batch_step(void *batch, int32_t n_steps);
+
+/* The autotuning outcome of the batch. */
+int fslbm_batch_info_get(void *batch, fslbm_batch_info *out);
+
+/* Wait for the batch's work and release its host resources. */
+int fslbm_batch_destroy(void *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,11 @@ class Scalars(C.Structure):
                 ("bucket", C.c_double), ("total_mass", C.c_double), ("n_topology", C.c_int64)]
 
 
+class BatchInfo(C.Structure):
+    _fields_ = [("bulk_threads", C.c_int32), ("order", C.c_int32), ("from_cache", C.c_int32),
+                ("pad", C.c_int32), ("cells", C.c_int64), ("probe_ms", C.c_float * 4)]
+
+
 class Timing(C.Structure):
     _fields_ = [("bulk_ms", C.c_double), ("iface_ms", C.c_double), ("convert_ms", C.c_double),
                 ("excess_ms", C.c_double), ("gather_ms", C.c_double), ("label_ms", C.c_double),
@@ -92,6 +97,17 @@ def lib() -> C.CDLL:
         L.fslbm_get_timing.argtypes = [P, C.POINTER(Timing)]
         L.fslbm_last_error.restype = C.c_char_p
         L.fslbm_last_error.argtypes = []
+        L.fslbm_batch_workspace_bytes.restype = C.c_size_t
+        L.fslbm_batch_workspace_bytes.argtypes = [C.c_int32]
+        L.fslbm_batch_create.restype = C.c_int
+        L.fslbm_batch_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_char_p, P,
+                                         C.c_size_t, P, C.POINTER(C.c_void_p)]
+        L.fslbm_batch_step.restype = C.c_int
+        L.fslbm_batch_step.argtypes = [P, C.c_int32]
+        L.fslbm_batch_info_get.restype = C.c_int
+        L.fslbm_batch_info_get.argtypes = [P, C.POINTER(BatchInfo)]
+        L.fslbm_batch_destroy.restype = C.c_int
+        L.fslbm_batch_destroy.argtypes = [P]
         _lib = L
     return _lib
 
@@ -256,6 +272,69 @@ class Domain:
     def close(self) -> None:
         if getattr(self, "handle", None):
             fslbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fslbm_batch_workspace_bytes(n_domains: int) -> int:
+    return int(lib().fslbm_batch_workspace_bytes(int(n_domains)))
+
+
+def fslbm_batch_create(handles, tuning_cache_path, workspace, stream=None):
+    """Batch over the given handles.  workspace: a CUDA uint8 tensor of at
+    least fslbm_batch_workspace_bytes(len(handles)) bytes."""
+    import torch
+
+    arr = (C.c_void_p * len(handles))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    st = stream if stream is not None else torch.cuda.current_stream(workspace.device)
+    b = C.c_void_p()
+    path = None if tuning_cache_path is None else str(tuning_cache_path).encode()
+    _check(lib().fslbm_batch_create(arr, len(handles), path, C.c_void_p(workspace.data_ptr()),
+                                    workspace.numel(), C.c_void_p(st.cuda_stream), C.byref(b)))
+    return b
+
+
+def fslbm_batch_step(batch, n_steps: int) -> None:
+    _check(lib().fslbm_batch_step(batch, int(n_steps)))
+
+
+def fslbm_batch_info_get(batch) -> dict:
+    info = BatchInfo()
+    _check(lib().fslbm_batch_info_get(batch, C.byref(info)))
+    return dict(bulk_threads=info.bulk_threads, order=info.order, from_cache=info.from_cache,
+                cells=info.cells, probe_ms=list(info.probe_ms))
+
+
+def fslbm_batch_destroy(batch) -> None:
+    _check(lib().fslbm_batch_destroy(batch))
+
+
+class Batch:
+    """Many domains advanced together (one graph launch per step)."""
+
+    def __init__(self, domains, tuning_cache_path=None, stream=None):
+        import torch
+
+        self.domains = list(domains)
+        nbytes = fslbm_batch_workspace_bytes(len(self.domains))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.domains[0].workspace.device)
+        self.handle = fslbm_batch_create([d.handle for d in self.domains], tuning_cache_path,
+                                         self.workspace, stream)
+
+    def step(self, n: int = 1) -> None:
+        fslbm_batch_step(self.handle, n)
+
+    def info(self) -> dict:
+        return fslbm_batch_info_get(self.handle)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            fslbm_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -17,12 +17,15 @@ ARCH = os.environ.get("FSLBM_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", f"-I{INCLUDE}", f"-I{CSRC}",
           # packed FP32 instructions stay off (not emitted from plain float code)
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# No FMA contraction in any precision: every kernel body computes in the
+# operation order of its source, so a domain gives bit-identical results
+# whether it is launched alone or in a batch (where the compiler would
+# otherwise contract differently), and the FP64 form keeps the operation
+# order of its definition.
 UNITS = {
-    # the FP64 form keeps the operation order of its definition: no FMA
-    # contraction
     "k_fp64.hip": ["-ffp-contract=off"],
-    "k_fp32.hip": [],
-    "k_fp16.hip": [],
+    "k_fp32.hip": ["-ffp-contract=off"],
+    "k_fp16.hip": ["-ffp-contract=off"],
     "api.hip": [],
 }
 

@@ -205,13 +205,19 @@ void build_devs(Ctx &c) {
   }
 }
 
-LaunchCfg make_cfg(const fslbm_params &p) {
+LaunchCfg make_cfg(const fslbm_params &p, int bulk_threads = 256) {
   LaunchCfg cfg;
-  cfg.bx = p.nx >= 256 ? 256 : ((p.nx + 63) / 64) * 64;
   const long long N = (long long)p.nx * p.ny * p.nz;
-  cfg.list_grid = (int)std::max<long long>(1, std::min<long long>((N + 255) / 256, 2048));
-  cfg.small_grid = (int)std::max<long long>(1, std::min<long long>((N + 255) / 256, 256));
-  cfg.cell_grid = (int)std::max<long long>(1, std::min<long long>((N + 255) / 256, 1024));
+  auto clampb = [&](long long per, long long cap) {
+    return (int)std::max<long long>(1, std::min<long long>((N + per - 1) / per, cap));
+  };
+  cfg.bulk_threads = bulk_threads;
+  cfg.blocks[G_BULK] = (int)((N + bulk_threads - 1) / bulk_threads);
+  cfg.blocks[G_LIST] = clampb(256, 2048);
+  cfg.blocks[G_SMALL] = clampb(256, 256);
+  cfg.blocks[G_TILE] = (int)((N + 4095) / 4096);
+  cfg.blocks[G_ONE] = 1;
+  cfg.blocks[G_CELL] = clampb(256, 1024);
   cfg.with_mass = 1;
   return cfg;
 }
@@ -228,6 +234,170 @@ std::vector<char> pack_real(const std::vector<double> &v, int bytes) {
     for (size_t k = 0; k < v.size(); ++k) o[k] = (float)v[k];
   }
   return out;
+}
+
+// ------------------------------------------------------------- batches
+
+struct Batch {
+  std::vector<Ctx *> dom;       // launch order
+  std::vector<int> base_cur;    // parity of every domain when the tables were built
+  Launchers L;
+  int precision = 0;
+  hipStream_t user_stream = nullptr;
+  hipStream_t stream = nullptr;  // own stream: captured and replayed
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  char *ws = nullptr;
+  Dev *d_devs[2] = {nullptr, nullptr};
+  int *d_off[G_COUNT] = {};
+  BatchCfg cfg[2];
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  fslbm_batch_info info{};
+};
+
+size_t batch_bytes(int nd) {
+  return align256(2 * (size_t)nd * sizeof(Dev)) + G_COUNT * align256((size_t)(nd + 1) * 4);
+}
+
+// Device tables for the current domain order and parities: the Dev of
+// every domain for the next step (relative parity 0) and the one after
+// (1), and per grid class the first block of every domain.
+int batch_tables(Batch &b, int bulk_threads) {
+  const int nd = (int)b.dom.size();
+  std::vector<Dev> devs(2 * (size_t)nd);
+  std::vector<int> off[G_COUNT];
+  for (int g = 0; g < G_COUNT; ++g) off[g].assign(nd + 1, 0);
+  b.base_cur.resize(nd);
+  for (int k = 0; k < nd; ++k) {
+    Ctx &c = *b.dom[k];
+    b.base_cur[k] = c.cur;
+    devs[k] = c.dev[c.cur];
+    devs[nd + k] = c.dev[c.cur ^ 1];
+    const LaunchCfg lc = make_cfg(c.P, bulk_threads);
+    for (int g = 0; g < G_COUNT; ++g) off[g][k + 1] = off[g][k] + lc.blocks[g];
+  }
+  char *p = b.ws;
+  b.d_devs[0] = (Dev *)p;
+  b.d_devs[1] = (Dev *)p + nd;
+  HIP_TRY(hipMemcpyAsync(p, devs.data(), devs.size() * sizeof(Dev), hipMemcpyHostToDevice, b.stream));
+  p += align256(2 * (size_t)nd * sizeof(Dev));
+  for (int g = 0; g < G_COUNT; ++g) {
+    b.d_off[g] = (int *)p;
+    HIP_TRY(hipMemcpyAsync(p, off[g].data(), (nd + 1) * 4, hipMemcpyHostToDevice, b.stream));
+    p += align256((size_t)(nd + 1) * 4);
+  }
+  HIP_TRY(hipStreamSynchronize(b.stream));
+  for (int r = 0; r < 2; ++r) {
+    BatchCfg &bc = b.cfg[r];
+    bc.devs = b.d_devs[r];
+    bc.nd = nd;
+    for (int g = 0; g < G_COUNT; ++g) {
+      bc.off[g] = b.d_off[g];
+      bc.total[g] = off[g][nd];
+    }
+    bc.bulk_threads = bulk_threads;
+    bc.with_mass = 1;
+  }
+  return FSLBM_OK;
+}
+
+void batch_drop_graphs(Batch &b) {
+  for (int r = 0; r < 2; ++r) {
+    if (b.exec[r]) hipGraphExecDestroy(b.exec[r]);
+    if (b.graph[r]) hipGraphDestroy(b.graph[r]);
+    b.exec[r] = nullptr;
+    b.graph[r] = nullptr;
+  }
+}
+
+// One graph per relative parity, each holding one whole step of every
+// domain (the kernels only; no memory operations are captured).
+int batch_capture(Batch &b) {
+  batch_drop_graphs(b);
+  for (int r = 0; r < 2; ++r) {
+    HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
+    for (int ph = 0; ph < PH_COUNT; ++ph) b.L.batch_phase(ph, b.cfg[r], b.stream);
+    HIP_TRY(hipStreamEndCapture(b.stream, &b.graph[r]));
+    HIP_TRY(hipGraphInstantiate(&b.exec[r], b.graph[r], nullptr, nullptr, 0));
+  }
+  return FSLBM_OK;
+}
+
+// Tuning key: precision and the sequence of domain extents (FNV-1a).
+std::string batch_key(const Batch &b) {
+  unsigned long long h = 1469598103934665603ull;
+  auto mix = [&](long long v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (unsigned long long)((v >> (8 * k)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  for (Ctx *c : b.dom) {
+    mix(c->P.nx);
+    mix(c->P.ny);
+    mix(c->P.nz);
+  }
+  char buf[96];
+  std::snprintf(buf, sizeof buf, "p%d-n%zu-%016llx", b.precision, b.dom.size(), h);
+  return buf;
+}
+
+bool batch_cache_lookup(const char *path, const std::string &key, int &threads, int &order) {
+  if (!path) return false;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char k[128];
+  int t, o;
+  bool found = false;
+  while (std::fscanf(f, "%127s %d %d", k, &t, &o) == 3)
+    if (key == k && (t == 128 || t == 256) && (o == 0 || o == 1)) {
+      threads = t;
+      order = o;
+      found = true;
+    }
+  std::fclose(f);
+  return found;
+}
+
+void batch_cache_store(const char *path, const std::string &key, int threads, int order) {
+  if (!path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d\n", key.c_str(), threads, order);
+  std::fclose(f);
+}
+
+// Average duration (ms) of the stream-collide probe over reps launches.
+int batch_probe(Batch &b, int reps, float &ms) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  for (int w = 0; w < 2; ++w) b.L.batch_bulk_probe(b.cfg[0], b.stream);
+  HIP_TRY(hipEventRecord(e0, b.stream));
+  for (int r = 0; r < reps; ++r) b.L.batch_bulk_probe(b.cfg[0], b.stream);
+  HIP_TRY(hipEventRecord(e1, b.stream));
+  HIP_TRY(hipEventSynchronize(e1));
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  ms /= reps;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return FSLBM_OK;
+}
+
+void batch_order(Batch &b, const std::vector<Ctx *> &given, int order) {
+  b.dom = given;
+  if (order == 1)
+    std::stable_sort(b.dom.begin(), b.dom.end(), [](const Ctx *x, const Ctx *y) { return x->N > y->N; });
+}
+
+void batch_free(Batch *b) {
+  if (!b) return;
+  if (b->stream) hipStreamSynchronize(b->stream);
+  batch_drop_graphs(*b);
+  if (b->ev_in) hipEventDestroy(b->ev_in);
+  if (b->ev_out) hipEventDestroy(b->ev_out);
+  if (b->stream) hipStreamDestroy(b->stream);
+  delete b;
 }
 
 int sync_and_check(Ctx &c) {
@@ -659,6 +829,138 @@ int fslbm_destroy(void *handle) {
   hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->events) hipEventDestroy(e);
   delete c;
+  return FSLBM_OK;
+}
+
+size_t fslbm_batch_workspace_bytes(int32_t n_domains) {
+  if (n_domains < 1) return 0;
+  return batch_bytes(n_domains);
+}
+
+int fslbm_batch_create(void *const *handles, int32_t n, const char *tuning_cache_path,
+                       void *device_workspace, size_t workspace_bytes, void *stream,
+                       void **out_batch) {
+  if (!out_batch) return fail(FSLBM_EINVAL, "out_batch is NULL");
+  *out_batch = nullptr;
+  if (!handles || n < 1) return fail(FSLBM_EINVAL, "no handles");
+  if (!device_workspace || ((uintptr_t)device_workspace & 255))
+    return fail(FSLBM_EINVAL, "device_workspace must be 256-byte aligned");
+  if (workspace_bytes < batch_bytes(n)) return fail(FSLBM_ENOMEM, "batch workspace too small");
+  std::vector<Ctx *> given(n);
+  for (int k = 0; k < n; ++k) {
+    if (!handles[k]) return fail(FSLBM_EINVAL, "a handle is NULL");
+    given[k] = (Ctx *)handles[k];
+    for (int j = 0; j < k; ++j)
+      if (given[j] == given[k]) return fail(FSLBM_EINVAL, "a handle is listed twice");
+    if (given[k]->P.precision != given[0]->P.precision)
+      return fail(FSLBM_EINVAL, "all domains of a batch must have the same precision");
+  }
+  Batch *b = new Batch();
+  b->precision = given[0]->P.precision;
+  b->L = given[0]->L;
+  b->user_stream = (hipStream_t)stream;
+  b->ws = (char *)device_workspace;
+  auto bail = [&](int code) {
+    std::string msg = g_err;
+    batch_free(b);
+    g_err = msg;
+    return code;
+  };
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+    fail(FSLBM_EDEVICE, "batch: stream or event creation failed");
+    return bail(FSLBM_EDEVICE);
+  }
+  // finish whatever the domains' own streams hold (creation uploads)
+  for (Ctx *c : given)
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+      fail(FSLBM_EDEVICE, "batch: domain stream sync failed");
+      return bail(FSLBM_EDEVICE);
+    }
+  long long cells = 0;
+  for (Ctx *c : given) cells += c->N;
+  b->info.cells = cells;
+  // autotuning: stream-collide block size and block-to-domain order
+  b->dom = given;
+  const std::string key = batch_key(*b);
+  int threads = 256, order = 0;
+  if (batch_cache_lookup(tuning_cache_path, key, threads, order)) {
+    b->info.from_cache = 1;
+  } else {
+    float best = 1e30f;
+    int ci = 0;
+    for (int t : {256, 128})
+      for (int o : {0, 1}) {
+        batch_order(*b, given, o);
+        int rc = batch_tables(*b, t);
+        float ms = 0.f;
+        if (rc == FSLBM_OK) rc = batch_probe(*b, 5, ms);
+        if (rc != FSLBM_OK) return bail(rc);
+        b->info.probe_ms[ci++] = ms;
+        if (ms < best) {
+          best = ms;
+          threads = t;
+          order = o;
+        }
+      }
+    batch_cache_store(tuning_cache_path, key, threads, order);
+  }
+  b->info.bulk_threads = threads;
+  b->info.order = order;
+  batch_order(*b, given, order);
+  int rc = batch_tables(*b, threads);
+  if (rc == FSLBM_OK) rc = batch_capture(*b);
+  if (rc != FSLBM_OK) return bail(rc);
+  *out_batch = b;
+  g_err.clear();
+  return FSLBM_OK;
+}
+
+int fslbm_batch_step(void *batch, int32_t n_steps) {
+  if (!batch) return fail(FSLBM_EINVAL, "batch is NULL");
+  if (n_steps < 0) return fail(FSLBM_EINVAL, "n_steps < 0");
+  Batch &b = *(Batch *)batch;
+  if (n_steps == 0) return FSLBM_OK;
+  // a domain stepped on its own since the tables were built shifts its
+  // parity: rebuild the tables and graphs
+  const int nd = (int)b.dom.size();
+  const int r0 = (b.dom[0]->cur - b.base_cur[0]) & 1;
+  bool same = true;
+  for (int k = 1; k < nd; ++k) same = same && (((b.dom[k]->cur - b.base_cur[k]) & 1) == r0);
+  int r = r0;
+  if (!same) {
+    int rc = batch_tables(b, b.info.bulk_threads);
+    if (rc == FSLBM_OK) rc = batch_capture(b);
+    if (rc != FSLBM_OK) return rc;
+    r = 0;
+  }
+  // order after the work already queued on the caller's and the domains'
+  // streams, and before whatever they queue next
+  std::vector<hipStream_t> streams{b.user_stream};
+  for (Ctx *c : b.dom)
+    if (std::find(streams.begin(), streams.end(), c->stream) == streams.end())
+      streams.push_back(c->stream);
+  for (hipStream_t st : streams) {
+    HIP_TRY(hipEventRecord(b.ev_in, st));
+    HIP_TRY(hipStreamWaitEvent(b.stream, b.ev_in, 0));
+  }
+  for (int s = 0; s < n_steps; ++s) HIP_TRY(hipGraphLaunch(b.exec[(r + s) & 1], b.stream));
+  HIP_TRY(hipEventRecord(b.ev_out, b.stream));
+  for (hipStream_t st : streams) HIP_TRY(hipStreamWaitEvent(st, b.ev_out, 0));
+  for (Ctx *c : b.dom) c->cur ^= (n_steps & 1);
+  return FSLBM_OK;
+}
+
+int fslbm_batch_info_get(void *batch, fslbm_batch_info *out) {
+  if (!batch || !out) return fail(FSLBM_EINVAL, "NULL argument");
+  *out = ((Batch *)batch)->info;
+  return FSLBM_OK;
+}
+
+int fslbm_batch_destroy(void *batch) {
+  if (!batch) return fail(FSLBM_EINVAL, "batch is NULL");
+  batch_free((Batch *)batch);
   return FSLBM_OK;
 }
 

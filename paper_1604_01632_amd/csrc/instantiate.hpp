@@ -1,81 +1,130 @@
-// Kernel launch sequence of one step for one precision.  Included by one
-// translation unit per precision.
+// Kernel launch sequence of one step for one precision, for one domain or
+// for a batch of domains.  Included by one translation unit per precision.
 #pragma once
 #include "kernels.hpp"
 #include "launch.hpp"
 
 namespace fslbm {
 
-template <class P>
-static void phase_impl(int ph, const Dev &d, const LaunchCfg &c, hipStream_t s) {
+// One kernel K of grid class G: for one domain or for the whole batch.
+template <class K>
+static inline void one(const Dev &d, const LaunchCfg &c, int g, hipStream_t s) {
+  if (c.blocks[g] > 0) k_one<K><<<c.blocks[g], K::THREADS, 0, s>>>(d);
+}
+template <class K>
+static inline void many(const BatchCfg &b, int g, hipStream_t s) {
+  if (b.total[g] > 0) k_many<K><<<b.total[g], K::THREADS, 0, s>>>(b.devs, b.off[g], b.nd);
+}
+
+// The kernels of each phase, in order, with their grid classes.  L is a
+// launcher object with `template <class K> void operator()(int g)`.
+template <class P, class L>
+static void phase_kernels(int ph, bool with_mass, int bulk_threads, L &&launch) {
   switch (ph) {
-    case PH_BULK: {
-      const int gx = (d.nx + c.bx - 1) / c.bx;
-      const unsigned nb = (unsigned)gx * (unsigned)d.ny * (unsigned)d.nz;
-      if (c.with_mass) k_bulk<P, true><<<nb, c.bx, 0, s>>>(d, gx);
-      else k_bulk<P, false><<<nb, c.bx, 0, s>>>(d, gx);
-      break;
-    }
     case PH_IFACE:
-      k_geom<P><<<c.list_grid, 256, 0, s>>>(d);
-      if (c.with_mass) k_iface<P, true><<<c.list_grid, 256, 0, s>>>(d);
-      else k_iface<P, false><<<c.list_grid, 256, 0, s>>>(d);
+      launch.template go<K_geom<P>>(G_LIST);
+      if (with_mass) launch.template go<K_iface<P, true>>(G_LIST);
+      else launch.template go<K_iface<P, false>>(G_LIST);
+      break;
+    case PH_BULK:
+      if (bulk_threads == 128) {
+        if (with_mass) launch.template go<K_bulk<P, true, 128>>(G_BULK);
+        else launch.template go<K_bulk<P, false, 128>>(G_BULK);
+      } else {
+        if (with_mass) launch.template go<K_bulk<P, true, 256>>(G_BULK);
+        else launch.template go<K_bulk<P, false, 256>>(G_BULK);
+      }
       break;
     case PH_CONVERT:
-      k_conv_types<P><<<c.small_grid, 256, 0, s>>>(d);
-      k_conv_init<P><<<c.small_grid, 256, 0, s>>>(d);
+      launch.template go<K_conv_types<P>>(G_SMALL);
+      launch.template go<K_conv_init<P>>(G_SMALL);
       break;
     case PH_EXCESS:
-      k_excess<P><<<c.small_grid, 256, 0, s>>>(d);
+      launch.template go<K_excess<P>>(G_SMALL);
       break;
-    case PH_GATHER: {
-      k_gather<P><<<c.list_grid, 256, 0, s>>>(d);
-      const int ntiles = (int)((d.N + LTILE - 1) / LTILE);
-      k_list_count<<<ntiles, 256, 0, s>>>(d);
-      k_list_scan<<<1, 1024, 0, s>>>(d, ntiles);
-      k_list_fill<<<ntiles, 256, 0, s>>>(d);
-      k_volumes<P><<<1, 1024, 0, s>>>(d);
+    case PH_GATHER:
+      launch.template go<K_gather<P>>(G_LIST);
+      launch.template go<K_list_count>(G_TILE);
+      launch.template go<K_list_scan>(G_ONE);
+      launch.template go<K_list_fill>(G_TILE);
+      launch.template go<K_volumes<P>>(G_ONE);
       break;
-    }
     case PH_LABEL:
-      k_label_init<<<c.cell_grid, 256, 0, s>>>(d);
-      k_label_union<<<c.cell_grid, 256, 0, s>>>(d);
-      k_label_roots<<<c.cell_grid, 256, 0, s>>>(d);
-      k_label_decide<<<c.cell_grid, 256, 0, s>>>(d);
-      k_label_assign<<<1, 1024, 0, s>>>(d);
-      k_label_accumulate<P><<<c.cell_grid, 256, 0, s>>>(d);
-      k_label_finish<<<1, 1024, 0, s>>>(d);
-      k_label_rewrite<<<c.cell_grid, 256, 0, s>>>(d);
+      launch.template go<K_label_init>(G_CELL);
+      launch.template go<K_label_union>(G_CELL);
+      launch.template go<K_label_roots>(G_CELL);
+      launch.template go<K_label_decide>(G_CELL);
+      launch.template go<K_label_assign>(G_ONE);
+      launch.template go<K_label_accumulate<P>>(G_CELL);
+      launch.template go<K_label_finish>(G_ONE);
+      launch.template go<K_label_rewrite>(G_CELL);
       break;
     case PH_BUBBLES:
-      k_bubbles<<<1, 1024, 0, s>>>(d);
+      launch.template go<K_bubbles>(G_ONE);
       break;
     default:
       break;
   }
 }
 
+struct OneLauncher {
+  const Dev &d;
+  const LaunchCfg &c;
+  hipStream_t s;
+  template <class K>
+  void go(int g) {
+    one<K>(d, c, g, s);
+  }
+};
+
+struct ManyLauncher {
+  const BatchCfg &b;
+  hipStream_t s;
+  template <class K>
+  void go(int g) {
+    many<K>(b, g, s);
+  }
+};
+
+template <class P>
+static void phase_impl(int ph, const Dev &d, const LaunchCfg &c, hipStream_t s) {
+  phase_kernels<P>(ph, c.with_mass != 0, c.bulk_threads, OneLauncher{d, c, s});
+}
+
+template <class P>
+static void batch_phase_impl(int ph, const BatchCfg &b, hipStream_t s) {
+  phase_kernels<P>(ph, b.with_mass != 0, b.bulk_threads, ManyLauncher{b, s});
+}
+
+template <class P>
+static void batch_bulk_probe_impl(const BatchCfg &b, hipStream_t s) {
+  if (b.bulk_threads == 128) many<K_bulk<P, false, 128>>(b, G_BULK, s);
+  else many<K_bulk<P, false, 256>>(b, G_BULK, s);
+}
+
 template <class P>
 static void init_feq_impl(const Dev &d, const LaunchCfg &c, const double *rho, const double *u,
                           hipStream_t s) {
-  k_init_feq<P><<<c.cell_grid, 256, 0, s>>>(d, rho, u);
+  k_init_feq<P><<<c.blocks[G_CELL], 256, 0, s>>>(d, rho, u);
 }
 
 template <class P>
 static void init_f_impl(const Dev &d, const LaunchCfg &c, const double *src, int a,
                         hipStream_t s) {
-  k_init_f<P><<<c.cell_grid, 256, 0, s>>>(d, src, a);
+  k_init_f<P><<<c.blocks[G_CELL], 256, 0, s>>>(d, src, a);
 }
 
 template <class P>
 static void export_impl(const Dev &d, const LaunchCfg &c, double *out, int what, hipStream_t s) {
-  k_export<P><<<c.cell_grid, 256, 0, s>>>(d, out, what);
+  k_export<P><<<c.blocks[G_CELL], 256, 0, s>>>(d, out, what);
 }
 
 template <class P>
 static Launchers make_launchers() {
   Launchers L;
   L.phase = phase_impl<P>;
+  L.batch_phase = batch_phase_impl<P>;
+  L.batch_bulk_probe = batch_bulk_probe_impl<P>;
   L.init_feq = init_feq_impl<P>;
   L.init_f = init_f_impl<P>;
   L.exportq = export_impl<P>;

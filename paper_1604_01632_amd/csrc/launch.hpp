@@ -4,12 +4,33 @@
 
 namespace fslbm {
 
+// Grid classes of the step kernels: how many blocks a domain gets.
+enum GridClass {
+  G_BULK = 0,  // stream-collide: one chunk of cells per block
+  G_LIST,      // interface-list kernels
+  G_SMALL,     // conversion-list kernels
+  G_TILE,      // interface-list rebuild: one tile of LTILE cells per block
+  G_ONE,       // single-block kernels (one per domain)
+  G_CELL,      // labelling kernels
+  G_COUNT
+};
+
 struct LaunchCfg {
-  int bx;         // threads per block of the bulk kernel (x extent)
-  int list_grid;  // blocks of the interface-list kernels
-  int small_grid; // blocks of the conversion-list kernels
-  int cell_grid;  // blocks of the cell-strided (labelling, init) kernels
-  int with_mass; // accumulate the total mass in the stream-collide kernels
+  int blocks[G_COUNT];
+  int bulk_threads;  // threads per stream-collide block (128 or 256)
+  int with_mass;     // accumulate the total mass in the stream-collide kernels
+};
+
+// Many domains in one launch per kernel: the Dev of every domain (for the
+// parity of the step) and, per grid class, the first block of every domain
+// (nd + 1 entries; the last is the total).  All pointers are device memory.
+struct BatchCfg {
+  const Dev *devs;
+  int nd;
+  const int *off[G_COUNT];
+  int total[G_COUNT];
+  int bulk_threads;
+  int with_mass;
 };
 
 // Phases of one step, in order; the host may record events between them.
@@ -17,6 +38,10 @@ enum Phase { PH_IFACE = 0, PH_BULK, PH_CONVERT, PH_EXCESS, PH_GATHER, PH_LABEL, 
 
 struct Launchers {
   void (*phase)(int ph, const Dev &d, const LaunchCfg &c, hipStream_t s);
+  void (*batch_phase)(int ph, const BatchCfg &b, hipStream_t s);
+  // stream-collide alone without the mass accumulator (autotuning: it only
+  // writes the new lattice and flags, which the next step rewrites)
+  void (*batch_bulk_probe)(const BatchCfg &b, hipStream_t s);
   void (*init_feq)(const Dev &d, const LaunchCfg &c, const double *rho, const double *u,
                    hipStream_t s);
   void (*init_f)(const Dev &d, const LaunchCfg &c, const double *src, int a, hipStream_t s);

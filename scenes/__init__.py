@@ -393,6 +393,79 @@ def config(name: str) -> Scene:
     raise KeyError(name)
 
 
+# ------------------------------------------------------ many-domain sets
+
+def _packed_spheres(rng, n, count, rmin, rmax, gap, wall_gap, tries=200):
+    """Up to `count` spheres with radii U[rmin, rmax], rejection-placed so
+    that interfaces keep `gap` cells between them and `wall_gap` cells from
+    the wall layers."""
+    nx, ny, nz = n
+    cs, rs = [], []
+    for _ in range(count):
+        for _ in range(tries):
+            r = rng.uniform(rmin, rmax)
+            lo = 1 + wall_gap + r
+            if any(lo > (m - lo) for m in n):
+                continue
+            c = np.array([rng.uniform(lo, m - lo) for m in n])
+            if all(np.linalg.norm(c - c2) >= r + r2 + gap for c2, r2 in zip(cs, rs)):
+                cs.append(c)
+                rs.append(r)
+                break
+    return cs, rs
+
+
+def _walled_sphere_domain(n, cs, rs, tau, sigma, g, ss, name):
+    """Walled box with gas spheres, hydrostatic liquid (rho = 1 at
+    mid-height) and every bubble in Laplace equilibrium with the liquid at
+    its centre: p = rho(z_c) / 3 + 2 sigma / R."""
+    nz = n[2]
+    pin = [(1.0 - 3.0 * g * ((nz - 1) / 2.0 - c[2])) / 3.0 + 2.0 * sigma / r for c, r in zip(cs, rs)]
+    sc = spheres(n=n, centers=cs, radii=rs, periodic=(0, 0, 0), walls=True, tau=tau,
+                 sigma=sigma, g=(0.0, 0.0, -g), p_init=pin, rho_l=1.0, ss=ss, steps=0, name=name)
+    return merge_ids_if_touching(sc)
+
+
+def batch_domains(count=256, seed=4, extents=(32, 48, 64, 80, 96), spheres_max=8,
+                  rmin=4.0, rmax=12.0, g=1e-5, tau=(0.55, 0.8), sigma=2e-3, ss=4):
+    """Independent walled domains of uneven sizes for the batched form: each
+    axis drawn uniformly from `extents`, 1..spheres_max gas spheres of
+    radius U[rmin, rmax] (at least 3 cells between sphere surfaces, 2 from
+    the walls), gravity g in -z, tau ~ U(tau), sigma fixed."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(count):
+        n = tuple(int(rng.choice(extents)) for _ in range(3))
+        cs, rs = _packed_spheres(rng, n, int(rng.integers(1, spheres_max + 1)), rmin, rmax, 3.0, 2.0)
+        t = float(rng.uniform(*tau))
+        out.append(_walled_sphere_domain(n, cs, rs, t, sigma, g, ss, f"batch-{k}"))
+    return out
+
+
+def serve_requests(count=512, seed=5, edge=(32, 192), spheres_max=64, rmin=3.0, rmax=10.0,
+                   horizon=(500, 5000), g=1e-5, tau=0.6, sigma=2e-3, ss=4):
+    """Request descriptions for the served form (scenes are built on
+    admission): cubic edge 16 * round(exp(U(ln 32, ln 192)) / 16), 1..64
+    packed spheres of radius U[3, 10], horizon U{500..5000} steps.  Returns
+    dicts with the seed of each request's scene."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    reqs = []
+    for k in range(count):
+        L = int(16 * round(math.exp(rng.uniform(math.log(edge[0]), math.log(edge[1]))) / 16))
+        reqs.append(dict(id=k, edge=max(16, L), spheres=int(rng.integers(1, spheres_max + 1)),
+                         horizon=int(rng.integers(horizon[0], horizon[1] + 1)),
+                         scene_seed=int(rng.integers(0, 2 ** 31 - 1))))
+    return reqs
+
+
+def request_scene(req, rmin=3.0, rmax=10.0, g=1e-5, tau=0.6, sigma=2e-3, ss=4):
+    """The scene of one served request (see serve_requests)."""
+    rng = np.random.Generator(np.random.PCG64(req["scene_seed"]))
+    n = (req["edge"],) * 3
+    cs, rs = _packed_spheres(rng, n, req["spheres"], rmin, rmax, 3.0, 2.0)
+    return _walled_sphere_domain(n, cs, rs, tau, sigma, g, ss, f"req-{req['id']}")
+
+
 # ------------------------------------------------------------ small scenes
 
 def random_blobs(n=(20, 18, 16), nblob=3, seed=0, periodic=(1, 1, 1), walls=False,
@@ -431,6 +504,20 @@ def merge_ids_if_touching(sc: Scene) -> Scene:
     t = sc.cell_type
     setc = (t == GAS) | (t == IFACE) | (t == INLET)
     bid = sc.bubble_id.copy()
+    if not any(per):
+        # no wrap-around: scipy's labelling with the 18-neighbour structure
+        from scipy import ndimage
+
+        st = ndimage.generate_binary_structure(3, 2)
+        lab, nlab = ndimage.label(setc.reshape(nz, ny, nx), structure=st)
+        lab = lab.reshape(-1)
+        if nlab:
+            mins = ndimage.minimum(bid, labels=lab, index=np.arange(1, nlab + 1))
+            bid[setc] = np.asarray(mins, dtype=np.int64)[lab[setc] - 1].astype(bid.dtype)
+        live = sorted(set(int(v) for v in np.unique(bid[setc])))
+        sc.bubble_id = bid
+        sc.bubbles = [b for b in sc.bubbles if b[0] in live]
+        return sc
     seen = np.zeros(len(t), dtype=bool)
     offs = list(_neighbours18(nx, ny, nz, per))
     for s in np.nonzero(setc)[0]:

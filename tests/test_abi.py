@@ -39,15 +39,17 @@ def test_exports_every_declared_symbol(binding):
 def test_struct_layout_matches_c(binding, tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "fslbm.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(fslbm_params),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fslbm_params),'
                    ' offsetof(fslbm_params, tau), offsetof(fslbm_params, max_bubbles),'
-                   ' sizeof(fslbm_bubble_init), sizeof(fslbm_bubble), sizeof(fslbm_scalars));'
+                   ' sizeof(fslbm_bubble_init), sizeof(fslbm_bubble), sizeof(fslbm_scalars),'
+                   ' sizeof(fslbm_timing), sizeof(fslbm_batch_info), offsetof(fslbm_batch_info, probe_ms));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     want = [C.sizeof(binding.Params), binding.Params.tau.offset, binding.Params.max_bubbles.offset,
-            C.sizeof(binding.BubbleInit), C.sizeof(binding.Bubble), C.sizeof(binding.Scalars)]
+            C.sizeof(binding.BubbleInit), C.sizeof(binding.Bubble), C.sizeof(binding.Scalars),
+            C.sizeof(binding.Timing), C.sizeof(binding.BatchInfo), binding.BatchInfo.probe_ms.offset]
     assert got == want
 
 
@@ -64,6 +66,8 @@ def test_workspace_bytes_host_only(binding):
     assert binding.fslbm_workspace_bytes(bad) == 0
     assert binding.fslbm_workspace_bytes(dict(p64, periodic=(0, 1, 1), nx=4)) == 0
     assert binding.fslbm_workspace_bytes(dict(p64, precision=7)) == 0
+    assert binding.fslbm_batch_workspace_bytes(0) == 0
+    assert binding.fslbm_batch_workspace_bytes(256) > 256 * 2 * 64
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
