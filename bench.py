@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -126,12 +128,138 @@ def copy_probe(mib: int, reps: int) -> int:
     return 0
 
 
+def bench_batched(args) -> int:
+    """Batched form: 256 walled domains of uneven sizes advanced together
+    (one graph launch per step) against the plain loop that steps each
+    domain on its own with the same kernels."""
+    import tempfile
+
+    import torch
+
+    import paper_1604_01632_amd as F
+    import scenes
+
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    scs = scenes.batch_domains(count=args.domains, seed=4)
+    log(f"[bench] {len(scs)} domains built in {time.perf_counter() - t:.1f} s")
+    doms = [F.Domain.from_scene(sc, args.precision) for sc in scs]
+    cells = sum(d.N for d in doms)
+    cache = os.path.join(tempfile.gettempdir(), "fslbm_batch_tuning.txt")
+    b = F.Batch(doms, tuning_cache_path=cache)
+    info = b.info()
+    log(f"[bench] batch of {len(doms)} domains, {cells} cells; tuning {info}")
+    b.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    batched = cells * args.steps / t_batch / 1e6
+    plain_steps = max(1, min(args.steps, args.plain_steps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in doms:
+        d.step(plain_steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain = cells * plain_steps / t_plain / 1e6
+    s = [d.read(("cell_type",))["scalars"] for d in doms]
+    bad = sum(1 for x in s if not np.isfinite(x["total_mass"]))
+    log(f"[bench] batched {batched:.1f} MLUPS ({t_batch / args.steps * 1e3:.3f} ms/step), plain loop "
+        f"{plain:.1f} MLUPS ({t_plain / plain_steps * 1e3:.3f} ms/step); non-finite domains {bad}")
+    out = {
+        "metric": METRIC, "value": round(batched, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_batch / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16dev": "f16-storage/f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"batched: {len(doms)} walled domains, extents 32..96 per axis, 1..8 "
+                               "gas spheres R 4..12 in Laplace equilibrium, g 1e-5, tau 0.55..0.8, "
+                               f"sigma 2e-3, {args.precision}, one graph launch per step",
+                   "cells": cells, "plain_loop_mlups": round(plain, 1),
+                   "plain_loop_steps": plain_steps, "speedup_vs_plain": round(batched / plain, 2),
+                   "tuning": info},
+        "roofline": None, "cpu_baseline": None,
+    }
+    b.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_served(args) -> int:
+    """Served form: a Poisson stream of foam requests at 80 % of the measured
+    capacity, continuous batching against the plain first-come-first-served
+    loop on the same arrival trace."""
+    import torch
+
+    import paper_1604_01632_amd as F
+    from paper_1604_01632_amd import serve
+    import scenes
+
+    torch.cuda.set_device(0)
+    descs = scenes.serve_requests(count=args.requests, seed=5)
+    work = np.array([d["edge"] ** 3 * d["horizon"] for d in descs], dtype=np.float64)
+    # capacity: aggregate rate of a full batch of sample requests
+    sample = [scenes.request_scene(d) for d in descs[:min(12, len(descs))]]
+    doms = [F.Domain.from_scene(sc, "fp32") for sc in sample]
+    b = F.Batch(doms, tuning_cache_path="")
+    b.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(60)
+    torch.cuda.synchronize()
+    cap_mlups = sum(d.N for d in doms) * 60 / (time.perf_counter() - t0) / 1e6
+    b.close()
+    for d in doms:
+        d.close()
+    del doms, b
+    rate = 0.8 * cap_mlups * 1e6 / work.mean()
+    rng = np.random.Generator(np.random.PCG64(55))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(descs)))
+    arrivals -= arrivals[0]
+    reqs = [serve.Request(d["id"], float(a), d["horizon"], (lambda d=d: scenes.request_scene(d)))
+            for d, a in zip(descs, arrivals)]
+    log(f"[bench] served: {len(reqs)} requests, capacity {cap_mlups:.0f} MLUPS, rate {rate:.3f}/s")
+    srv = serve.Server("fp32", max_active=args.max_active, quantum=args.quantum)
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    s_srv = serve.summary(res, time.perf_counter() - t0)
+    log(f"[bench] continuous batching: {s_srv}")
+    t0 = time.perf_counter()
+    res_fifo = serve.run_fifo(reqs, "fp32")
+    s_fifo = serve.summary(res_fifo, time.perf_counter() - t0)
+    log(f"[bench] plain loop: {s_fifo}")
+    by = {r.id: r for r in res_fifo}
+    same = all(np.array_equal(r.bubbles["volume"], by[r.id].bubbles["volume"])
+               and r.scalars == by[r.id].scalars for r in res)
+    out = {
+        "metric": METRIC, "value": round(s_srv["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": int(sum(d["horizon"] for d in descs)), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"served: {len(reqs)} foam requests, cubic edges 32..192 "
+                               "(log-uniform, multiples of 16), 1..64 spheres R 3..10, horizons "
+                               "500..5000, Poisson arrivals at 80 % of capacity, fp32",
+                   "p50_latency_s": round(s_srv["p50_s"], 3), "p99_latency_s": round(s_srv["p99_s"], 3),
+                   "plain_p50_latency_s": round(s_fifo["p50_s"], 3),
+                   "plain_p99_latency_s": round(s_fifo["p99_s"], 3),
+                   "plain_mlups": round(s_fifo["mlups"], 1), "capacity_mlups": round(cap_mlups, 1),
+                   "arrival_rate_per_s": round(rate, 4), "results_same_alone_and_mixed": bool(same)},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--workload", default="p1")
+    ap.add_argument("--workload", default="p1",
+                    help="p1 (default: 256^3 thread rupture), c1/c2/c3, batched, served")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16dev"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -139,6 +267,12 @@ def main() -> int:
                     help="time the window without per-phase events (no roofline figure)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter scaling) and exit")
+    ap.add_argument("--domains", type=int, default=256, help="batched workload: domains")
+    ap.add_argument("--plain-steps", type=int, default=50,
+                    help="batched workload: steps of the plain per-domain loop")
+    ap.add_argument("--requests", type=int, default=48, help="served workload: requests")
+    ap.add_argument("--max-active", type=int, default=64, help="served workload: slots")
+    ap.add_argument("--quantum", type=int, default=100, help="served workload: steps per decision")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -147,6 +281,10 @@ def main() -> int:
 
     if args.copy_probe:
         return copy_probe(args.copy_probe, 5)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "served":
+        return bench_served(args)
 
     import numpy as np
     import torch

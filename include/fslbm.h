@@ -204,8 +204,10 @@ const char *fslbm_last_error(void);
  * decreasing size) are chosen by timing the stream-collide kernel of the
  * batch on the live state (a probe without the mass accumulator that only
  * writes buffers the next step rewrites).  The choice is appended to the
- * text file tuning_cache_path (may be NULL) under a key made of the
- * precision and the domain extents, and read from it next time.
+ * text file tuning_cache_path (may be NULL: tune without caching) under a
+ * key made of the precision and the domain extents, and read from it next
+ * time.  An empty string "" skips tuning (256 threads, domains as given),
+ * for callers that rebuild batches often.
  * --------------------------------------------------------------------- */
 
 /* Device bytes of the batch tables for n_domains (0 if n_domains < 1). */

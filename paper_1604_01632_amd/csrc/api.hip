@@ -885,7 +885,9 @@ int fslbm_batch_create(void *const *handles, int32_t n, const char *tuning_cache
   b->dom = given;
   const std::string key = batch_key(*b);
   int threads = 256, order = 0;
-  if (batch_cache_lookup(tuning_cache_path, key, threads, order)) {
+  if (tuning_cache_path && !tuning_cache_path[0]) {
+    // "": no tuning (callers that rebuild batches often)
+  } else if (batch_cache_lookup(tuning_cache_path, key, threads, order)) {
     b->info.from_cache = 1;
   } else {
     float best = 1e30f;

@@ -97,12 +97,13 @@ def _subsample_fraction(cx, cy, cz, gas_fn, ss):
     return out
 
 
-def _gas_fraction(nx, ny, nz, gas_fn, band_fn, ss):
+def _gas_fraction(nx, ny, nz, gas_fn, band_fn, ss, band=None):
     """Gas volume fraction per cell.  band_fn(xc, yc, zc) returns
     (-1: certainly liquid, +1: certainly gas, 0: needs sub-sampling) using
-    cell centres."""
+    cell centres (or `band` is given precomputed)."""
     x, y, z = _grid(nx, ny, nz)
-    band = band_fn(x + 0.5, y + 0.5, z + 0.5)
+    if band is None:
+        band = band_fn(x + 0.5, y + 0.5, z + 0.5)
     frac = np.where(band > 0, 1.0, 0.0)
     cand = np.nonzero(band == 0)[0]
     if len(cand):
@@ -219,7 +220,24 @@ def spheres(n=(32, 32, 32), centers=((16.0, 16.0, 16.0),), radii=(8.0,), periodi
             out = np.where((np.abs(d - rs[k]) <= h) & (out != 1), 0, out)
         return out
 
-    gas = _gas_fraction(nx, ny, nz, gas_fn, band_fn, ss)
+    band = None
+    if not any(per):
+        # no wrap-around: each sphere can only mark cells in its bounding
+        # box (the same marks as band_fn, computed box by box)
+        band = np.full(nx * ny * nz, -1, dtype=np.int8)
+        b3 = band.reshape(nz, ny, nx)
+        for k in range(len(rs)):
+            lo = [max(0, int(math.floor(cs[k, a] - rs[k] - h)) - 1) for a in range(3)]
+            hi = [min(m, int(math.ceil(cs[k, a] + rs[k] + h)) + 2) for a, m in enumerate(n)]
+            if any(l >= u for l, u in zip(lo, hi)):
+                continue
+            zz, yy, xx = np.meshgrid(np.arange(lo[2], hi[2]), np.arange(lo[1], hi[1]),
+                                     np.arange(lo[0], hi[0]), indexing="ij")
+            d = np.sqrt(dist2(xx + 0.5, yy + 0.5, zz + 0.5, k))
+            sub = b3[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+            sub[...] = np.where(d + h < rs[k], 1, sub)
+            sub[...] = np.where((np.abs(d - rs[k]) <= h) & (sub != 1), 0, sub)
+    gas = _gas_fraction(nx, ny, nz, gas_fn, band_fn, ss, band)
     phi = 1.0 - gas
     fixed = np.full(nx * ny * nz, 255, dtype=np.uint8)
     x, y, z = _grid(nx, ny, nz)
