@@ -861,68 +861,102 @@ struct K_conv_types {
 // neighbours that were interface or liquid at t (recovered from their
 // post-collision values), m = 0, ID kept.  From liquid: m = rho of its own
 // post-collision values, the smallest bubble ID of its emptied neighbours.
+// D3Q19 velocities for runtime direction indices (one direction per lane).
+__constant__ int8_t C19[3][Q] = {
+    {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1},
+    {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1}};
+
+// Three new cells per wave, 18 lanes per cell (lanes 54..63 idle): lane q
+// of a cell's group looks at its neighbour in direction q + 1 (loads and
+// moments in parallel); the group's first lane then adds the 18
+// contributions in direction order, so sums keep the order of their
+// definition.
 template <class P>
 struct K_conv_init {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   using R = typename P::R;
   const int n = d.sc->n_new;
-  for (int k = bk.id * blockDim.x + threadIdx.x; k < n; k += bk.n * blockDim.x) {
-    const long long i = d.nlist[k];
-    int x, y, z;
-    coords(d, i, x, y, z);
-    const uint8_t t = d.flag_src[i] & TYPE_MASK;
-    if (t == T_GAS) {
-      R rs = (R)0, us[3] = {(R)0, (R)0, (R)0};
-      int cnt = 0;
-      for (int a = 1; a < Q; ++a) {
-        const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
-        const uint8_t tj = d.flag_src[j] & TYPE_MASK;
-        if (!(tj == T_IFACE || tj == T_LIQ)) continue;
-        R v[Q];
+  const int lane = (int)threadIdx.x & 63;
+  const int g = lane / 18, q = lane % 18, a = q + 1;
+  const int wave = (bk.id * (int)blockDim.x + (int)threadIdx.x) >> 6;
+  const int nwaves = (bk.n * (int)blockDim.x) >> 6;
+  for (int base = 3 * wave; base < n; base += 3 * nwaves) {
+    const int k = base + g;
+    const bool act = g < 3 && k < n;
+    long long i = 0;
+    uint8_t t = T_LIQ;
+    int x = 0, y = 0, z = 0;
+    R cr = (R)0, cu[3] = {(R)0, (R)0, (R)0};
+    int valid = 0, eid = INT_MAX, eslot = -1;
+    if (act) {
+      i = d.nlist[k];
+      t = d.flag_src[i] & TYPE_MASK;
+      coords(d, i, x, y, z);
+      const long long j = nbr(d, x, y, z, C19[0][a], C19[1][a], C19[2][a]);
+      const uint8_t tj = d.flag_src[j] & TYPE_MASK;
+      if (t == T_GAS) {
+        if (tj == T_IFACE || tj == T_LIQ) {
+          R v[Q];
 #pragma unroll
-        for (int c = 0; c < Q; ++c) v[c] = ld<P>(d.f_dst, c, d.N, j);
-        R r, dr, uj[3];
-        recover<P>(d, v, r, dr, uj);
-        rs += P::EXACT ? r : dr;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) us[c] += uj[c];
+          for (int c = 0; c < Q; ++c) v[c] = ld<P>(d.f_dst, c, d.N, j);
+          R r, dr;
+          recover<P>(d, v, r, dr, cu);
+          cr = P::EXACT ? r : dr;
+          valid = 1;
+        }
+      } else if (tj == T_IFACE && (d.flag_dst[j] & TYPE_MASK) == T_GAS) {
+        eslot = d.bslot[j];
+        eid = d.b_id[eslot];
+      }
+    }
+    // ordered sums (all lanes take part in the shuffles)
+    R rs = (R)0, us[3] = {(R)0, (R)0, (R)0};
+    int cnt = 0, best_id = INT_MAX, best_slot = -1;
+    const int g0 = (g < 3 ? g : 2) * 18;
+    for (int qq = 0; qq < 18; ++qq) {
+      const int src = g0 + qq;
+      const R vr = __shfl(cr, src, 64);
+      const R v0 = __shfl(cu[0], src, 64), v1 = __shfl(cu[1], src, 64), v2 = __shfl(cu[2], src, 64);
+      const int vv = __shfl(valid, src, 64);
+      const int ve = __shfl(eid, src, 64), vs = __shfl(eslot, src, 64);
+      if (vv) {
+        rs += vr;
+        us[0] += v0;
+        us[1] += v1;
+        us[2] += v2;
         ++cnt;
       }
-      const R mean = rs / (R)cnt;
-      const R rb = P::EXACT ? mean : (R)1 + mean;
-      const R ubar[3] = {us[0] / (R)cnt, us[1] / (R)cnt, us[2] / (R)cnt};
-      R fe[Q];
-      eqv<P>(rb, P::EXACT ? rb - (R)1 : mean, ubar, fe);
-#pragma unroll
-      for (int c = 0; c < Q; ++c) st<P>(d.f_dst, c, d.N, i, fe[c]);
-      ((R *)d.rhoI)[i] = rb;
-      ((R *)d.mass)[i] = (R)0;
-      atomicAdd((unsigned long long *)&d.b_ngas[d.bslot[i]], (unsigned long long)-1ll);
-    } else {
-      int best_slot = -1, best_id = INT_MAX;
-      for (int a = 1; a < Q; ++a) {
-        const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
-        const bool emptied = (d.flag_src[j] & TYPE_MASK) == T_IFACE &&
-                             (d.flag_dst[j] & TYPE_MASK) == T_GAS;
-        if (!emptied) continue;
-        const int s = d.bslot[j];
-        const int id = d.b_id[s];
-        if (id < best_id) {
-          best_id = id;
-          best_slot = s;
-        }
+      if (ve < best_id) {
+        best_id = ve;
+        best_slot = vs;
       }
-      R v[Q];
-#pragma unroll
-      for (int c = 0; c < Q; ++c) v[c] = ld<P>(d.f_dst, c, d.N, i);
-      R r, dr, uu[3];
-      recover<P>(d, v, r, dr, uu);
-      ((R *)d.mass)[i] = r;
-      ((R *)d.rhoI)[i] = r;
-      d.bslot[i] = best_slot;
     }
-    release_cell(d, i);
+    if (act && q == 0) {
+      if (t == T_GAS) {
+        const R mean = rs / (R)cnt;
+        const R rb = P::EXACT ? mean : (R)1 + mean;
+        const R ubar[3] = {us[0] / (R)cnt, us[1] / (R)cnt, us[2] / (R)cnt};
+        R fe[Q];
+        eqv<P>(rb, P::EXACT ? rb - (R)1 : mean, ubar, fe);
+#pragma unroll
+        for (int c = 0; c < Q; ++c) st<P>(d.f_dst, c, d.N, i, fe[c]);
+        ((R *)d.rhoI)[i] = rb;
+        ((R *)d.mass)[i] = (R)0;
+        atomicAdd((unsigned long long *)&d.b_ngas[d.bslot[i]], (unsigned long long)-1ll);
+      } else {
+        R v[Q];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) v[c] = ld<P>(d.f_dst, c, d.N, i);
+        R r, dr, uu[3];
+        recover<P>(d, v, r, dr, uu);
+        ((R *)d.mass)[i] = r;
+        ((R *)d.rhoI)[i] = r;
+        d.bslot[i] = best_slot;
+      }
+      release_cell(d, i);
+    }
   }
 }
 };
