@@ -406,6 +406,7 @@ int sync_and_check(Ctx &c) {
   HIP_TRY(hipMemcpy(&sc, c.dev[0].sc, sizeof sc, hipMemcpyDeviceToHost));
   if (sc.err & ERR_CAPACITY) return fail(FSLBM_ECAPACITY, "bubble table full (max_bubbles)");
   if (sc.err & ERR_NONFINITE) return fail(FSLBM_ENUMERIC, "non-finite total mass");
+  if (sc.err & ERR_RANGE) return fail(FSLBM_ENUMERIC, "conversion candidate list overflow");
   return FSLBM_OK;
 }
 

@@ -43,10 +43,10 @@ static void phase_kernels(int ph, bool with_mass, int bulk_threads, L &&launch) 
       launch.template go<K_excess<P>>(G_SMALL);
       break;
     case PH_GATHER:
-      launch.template go<K_gather<P>>(G_LIST);
       launch.template go<K_list_count>(G_TILE);
       launch.template go<K_list_scan>(G_ONE);
       launch.template go<K_list_fill>(G_TILE);
+      launch.template go<K_gather<P>>(G_LIST);
       launch.template go<K_volumes<P>>(G_ONE);
       break;
     case PH_LABEL:

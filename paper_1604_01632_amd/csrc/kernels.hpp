@@ -802,8 +802,13 @@ struct K_iface {
       if (WITH_MASS) mass.add(m, FX_VOL);
       cand = (nf & (CAND_F | CAND_E)) != 0;
     }
+    // at most one entry per cell and step (the counter is reset at the
+    // end of the step); the bound only guards the list
     const int pos = wave_append(cand, &d.sc->n_cand);
-    if (cand) d.clist[pos] = (int)i;
+    if (cand) {
+      if (pos < (int)d.N) d.clist[pos] = (int)i;
+      else atomicOr(&d.sc->err, ERR_RANGE);
+    }
   }
   if (WITH_MASS) block_fx_add(mass, d.mass_acc, bk.id % SUB_MASS);
 }
@@ -1084,65 +1089,64 @@ struct K_excess {
 
 // -------------------------------------------------------------- k_gather
 
-// Final interface cells pull the excess of converted neighbours (in
-// direction order), recompute phi = m / rho and add 1 - phi to their
-// bubble's volume.
+// Over the interface list of t+1 (in cell order): cells that received
+// excess (tagged by k_excess) and new interface cells pull the excess of
+// converted neighbours (in direction order) and recompute phi = m / rho;
+// every cell adds 1 - phi to its bubble's volume (Sec. 2.3).
 template <class P>
 struct K_gather {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   using R = typename P::R;
   const int sub = bk.id % SUB;
-  const int ni = d.sc->n_il_src, nn = d.sc->n_new;
-  for (int base = bk.id * blockDim.x; base < ni + nn; base += bk.n * blockDim.x) {
+  const int n = d.sc->n_il_dst;  // interface list of t+1, rebuilt before this kernel
+  for (int base = bk.id * blockDim.x; base < n; base += bk.n * blockDim.x) {
     const int k = base + threadIdx.x;
     int key = -1;
     long long v[VACC] = {0, 0, 0, 0, 0, 1};
-    long long i = 0;
-    if (k < ni + nn) {
-      i = k < ni ? d.ilist_src[k] : d.nlist[k - ni];
+    if (k < n) {
+      const long long i = d.ilist_dst[k];
       const uint8_t fd = d.flag_dst[i];
-      if ((fd & TYPE_MASK) == T_IFACE) {
-        R ph;
-        if ((fd & GATHER) || k >= ni) {
+      R ph;
+      if ((fd & GATHER) || (d.flag_src[i] & TYPE_MASK) != T_IFACE) {
+        // a receiver of excess or a new interface cell
+        R add = (R)0;
+        bool touched = false;
+        if (fd & GATHER) {
           int x, y, z;
           coords(d, i, x, y, z);
-          R add = (R)0;
-          bool touched = false;
-          if (fd & GATHER) {
-            const Nb3 nb(d, x, y, z);
-            bool conv[Q];
-            R ex[Q];
+          const Nb3 nb(d, x, y, z);
+          bool conv[Q];
+          R ex[Q];
 #pragma unroll
-            for (int a = 1; a < Q; ++a) {
-              const long long j = nb.at(d, CX[a], CY[a], CZ[a]);
-              const uint8_t t0 = d.flag_src[j] & TYPE_MASK;
-              const uint8_t t1 = d.flag_dst[j] & TYPE_MASK;
-              conv[a] = t0 == T_IFACE && (t1 == T_LIQ || t1 == T_GAS);
-              ex[a] = ((const R *)d.excess)[j];
-            }
+          for (int a = 1; a < Q; ++a) {
+            const long long j = nb.at(d, CX[a], CY[a], CZ[a]);
+            const uint8_t t0 = d.flag_src[j] & TYPE_MASK;
+            const uint8_t t1 = d.flag_dst[j] & TYPE_MASK;
+            conv[a] = t0 == T_IFACE && (t1 == T_LIQ || t1 == T_GAS);
+            ex[a] = ((const R *)d.excess)[j];
+          }
 #pragma unroll
-            for (int a = 1; a < Q; ++a) {
-              add += conv[a] ? ex[a] : (R)0;
-              touched = touched || conv[a];
-            }
+          for (int a = 1; a < Q; ++a) {
+            add += conv[a] ? ex[a] : (R)0;
+            touched = touched || conv[a];
           }
-          R m = ((R *)d.mass)[i];
-          if (touched) {
-            m += add;
-            ((R *)d.mass)[i] = m;
-          }
-          ph = m / ((const R *)d.rhoI)[i];
-          ((R *)d.phi_dst)[i] = ph;
-        } else {
-          // untouched interface cell: phi = m / rho as written by k_iface
-          ph = ((const R *)d.phi_dst)[i];
         }
-        key = d.bslot[i];
-        const ExTerm t = ex_split(1.0 - (double)ph);
-#pragma unroll
-        for (int c = 0; c < EX_WORDS; ++c) v[c] = t.w[c];
+        R m = ((R *)d.mass)[i];
+        if (touched) {
+          m += add;
+          ((R *)d.mass)[i] = m;
+        }
+        ph = m / ((const R *)d.rhoI)[i];
+        ((R *)d.phi_dst)[i] = ph;
+      } else {
+        // untouched interface cell: phi = m / rho as written by k_iface
+        ph = ((const R *)d.phi_dst)[i];
       }
+      key = d.bslot[i];
+      const ExTerm t = ex_split(1.0 - (double)ph);
+#pragma unroll
+      for (int c = 0; c < EX_WORDS; ++c) v[c] = t.w[c];
     }
     wave_add_by_key<VACC>(key, v, d.b_vacc, SUB, sub);
   }
@@ -1156,16 +1160,32 @@ struct K_gather {
 // of the next step see spatially coherent cells in every wave.
 constexpr int LTILE = 4096;
 
+// Each thread of a tile block reads 16 consecutive flag bytes with one
+// 16-byte load (tiles are 16-byte aligned; the ragged end of the box is
+// read byte by byte).
+__device__ __forceinline__ uint32_t iface_bits16(const Dev &d, long long i0) {
+  uint32_t bits = 0;
+  if (i0 + 16 <= d.N) {
+    const uint4 v = *(const uint4 *)(d.flag_dst + i0);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        bits |= (uint32_t)((((w[q] >> (8 * b)) & TYPE_MASK) == T_IFACE) ? 1u : 0u) << (4 * q + b);
+  } else {
+    for (int b = 0; b < 16; ++b)
+      if (i0 + b < d.N && (d.flag_dst[i0 + b] & TYPE_MASK) == T_IFACE) bits |= 1u << b;
+  }
+  return bits;
+}
+
 struct K_list_count {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   __shared__ int part[4];
-  const long long base = (long long)bk.id * LTILE;
-  int c = 0;
-  for (int k = threadIdx.x; k < LTILE; k += blockDim.x) {
-    const long long i = base + k;
-    if (i < d.N && (d.flag_dst[i] & TYPE_MASK) == T_IFACE) ++c;
-  }
+  const long long i0 = (long long)bk.id * LTILE + 16 * (long long)threadIdx.x;
+  int c = i0 < d.N ? __popc(iface_bits16(d, i0)) : 0;
   c = (int)wave_sum((long long)c);
   if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = c;
   __syncthreads();
@@ -1205,26 +1225,31 @@ struct K_list_scan {
 struct K_list_fill {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
-  __shared__ int wcount[4];
-  const long long base = (long long)bk.id * LTILE;
-  int run = d.tileoff[bk.id];
-  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-  for (int k0 = 0; k0 < LTILE; k0 += blockDim.x) {
-    const long long i = base + k0 + threadIdx.x;
-    const bool pred = i < d.N && (d.flag_dst[i] & TYPE_MASK) == T_IFACE;
-    const unsigned long long m = __ballot(pred);
-    if (lane == 0) wcount[w] = (int)__popcll(m);
-    __syncthreads();
-    int before = 0;
-    for (int k = 0; k < w; ++k) before += wcount[k];
-    const int total = wcount[0] + wcount[1] + wcount[2] + wcount[3];
-    if (pred) {
-      const int pos = run + before + (int)__popcll(m & ((1ull << lane) - 1ull));
+  __shared__ int wsum[4];
+  const long long i0 = (long long)bk.id * LTILE + 16 * (long long)threadIdx.x;
+  const uint32_t bits = i0 < d.N ? iface_bits16(d, i0) : 0u;
+  const int c = __popc(bits);
+  // exclusive prefix of the per-thread counts over the block, in thread
+  // (= cell) order
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  int incl = c;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int before = 0;
+  for (int k = 0; k < w; ++k) before += wsum[k];
+  int pos = d.tileoff[bk.id] + before + incl - c;
+  for (int b = 0; b < 16; ++b) {
+    if ((bits >> b) & 1u) {
+      const long long i = i0 + b;
       d.ilist_dst[pos] = (int)i;
       d.islot[i] = pos;
+      ++pos;
     }
-    run += total;
-    __syncthreads();
   }
 }
 };
