@@ -84,6 +84,20 @@ __device__ __forceinline__ void st(void *f, int a, long long N, long long i, typ
   ((typename P::S *)f)[a * N + i] = (typename P::S)v;
 }
 
+// Streaming store of a stored value (non-temporal; half values by their
+// 16-bit pattern).
+template <class P>
+__device__ __forceinline__ void st_stream(void *f, int a, long long N, long long i,
+                                          typename P::R v) {
+  using S = typename P::S;
+  S *p = (S *)f + a * N + i;
+  if constexpr (sizeof(S) == 2) {
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, (S)v), (unsigned short *)p);
+  } else {
+    __builtin_nontemporal_store((S)v, p);
+  }
+}
+
 // ------------------------------------------------------------- geometry
 
 // Periodic wrap by adding or subtracting the extent (no integer division;
@@ -679,8 +693,11 @@ struct K_bulk {
 #pragma unroll
       for (int a = 0; a < Q; ++a) f[a] = (R)0;
     }
+    // the new lattice is written once and read only in the next step:
+    // non-temporal stores keep it from evicting the interface data that the
+    // following kernels read from the caches
 #pragma unroll
-    for (int a = 0; a < Q; ++a) st<P>(d.f_dst, a, d.N, i, f[a]);
+    for (int a = 0; a < Q; ++a) st_stream<P>(d.f_dst, a, d.N, i, f[a]);
     d.flag_dst[i] = nfl;
   } else if (in) {
     d.flag_dst[i] = fl & (STATIC_BITS | TYPE_MASK);
@@ -1397,20 +1414,72 @@ __device__ __forceinline__ void uf_union(int32_t *lab, int a, int b) {
 struct K_label_init {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
+  __shared__ int wsum[4];
+  __shared__ int base_sh;
   const int run = d.sc->label_run;
   if (!run) return;
   const bool all = run >= 2;
-  for (long long base = (long long)bk.id * blockDim.x; base < d.N;
-       base += (long long)bk.n * blockDim.x) {
-    const long long i = base + threadIdx.x;
-    bool in = false;
-    if (i < d.N) {
-      in = in_gas_region(d.flag_dst[i] & TYPE_MASK) && (all || d.b_affect[d.bslot[i]]);
-      d.lab[i] = in ? (int)i : -1;
-      if (in) d.aux2[i] = 0;
+  const int ntiles = (int)((d.N + LTILE - 1) / LTILE);
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  // tiles of LTILE cells, 16 consecutive cells per thread
+  for (int tile = bk.id; tile < ntiles; tile += bk.n) {
+    const long long i0 = (long long)tile * LTILE + 16 * (long long)threadIdx.x;
+    uint32_t bits = 0;
+    if (i0 < d.N) {
+      uint8_t tt[16];
+      if (i0 + 16 <= d.N) {
+        const uint4 v = *(const uint4 *)(d.flag_dst + i0);
+        const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) tt[q] = (uint8_t)((wd[q / 4] >> (8 * (q % 4))) & TYPE_MASK);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          tt[q] = i0 + q < d.N ? (uint8_t)(d.flag_dst[i0 + q] & TYPE_MASK) : (uint8_t)T_WALL;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (in_gas_region(tt[q]) && (all || d.b_affect[d.bslot[i0 + q]])) bits |= 1u << q;
+      // initial labels: the first cell of the cell's x-run inside the
+      // 16-cell chunk (a smaller index of the same component), so that a
+      // row segment starts as one tree; -1 outside the set
+      int x = (int)(i0 % d.nx);
+      int start = -1;
+      for (int q = 0; q < 16 && i0 + q < d.N; ++q) {
+        const long long i = i0 + q;
+        if (x == 0) start = -1;
+        if ((bits >> q) & 1u) {
+          if (start < 0) start = (int)i;
+          d.lab[i] = start;
+          d.aux2[i] = 0;
+        } else {
+          d.lab[i] = -1;
+          start = -1;
+        }
+        if (++x == d.nx) x = 0;
+      }
     }
-    const int pos = wave_append(in, &d.sc->n_lab);
-    if (in) d.clist[pos] = (int)i;
+    // list the set cells: one atomic per tile, cell order inside the tile
+    const int c = __popc(bits);
+    int incl = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+      base_sh = tot ? atomicAdd(&d.sc->n_lab, tot) : 0;
+    }
+    __syncthreads();
+    int before = 0;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    int pos = base_sh + before + incl - c;
+    for (int q = 0; q < 16; ++q)
+      if ((bits >> q) & 1u) d.clist[pos++] = (int)(i0 + q);
+    __syncthreads();
   }
   const long long t0 = (long long)bk.id * blockDim.x + threadIdx.x;
   for (long long t = t0; t < d.max_bubbles; t += (long long)bk.n * blockDim.x) {
@@ -1434,7 +1503,10 @@ struct K_label_union {
     // one direction of every opposite pair covers every edge once
     for (int a = 1; a < Q; a += 2) {
       const long long j = nbr_checked(d, x, y, z, CX[a], CY[a], CZ[a]);
-      if (j < 0 || d.lab[j] < 0) continue;
+      if (j < 0) continue;
+      const int lj = d.lab[j];
+      // outside the set, or already pointing to the same cell (one tree)
+      if (lj < 0 || lj == d.lab[i]) continue;
       uf_union(d.lab, (int)i, (int)j);
     }
   }
