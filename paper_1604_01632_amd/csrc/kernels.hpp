@@ -861,20 +861,36 @@ struct K_conv_types {
       if (F) d.flag_dst[i] = (uint8_t)((fd & ~TYPE_MASK) | T_LIQ);
       if (E) d.flag_dst[i] = (uint8_t)((fd & ~TYPE_MASK) | T_GAS);
     }
-    for (int a = 1; a < Q; ++a) {
-      bool claim = false;
-      long long j = 0;
-      if (F || E) {
-        j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
+    // neighbours that become interface cells: all claims are issued
+    // together, then the claimed cells are appended with one atomic per
+    // wave
+    uint32_t won = 0;
+    if (F || E) {
+#pragma unroll
+      for (int a = 1; a < Q; ++a) {
+        const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
         const uint8_t tj = d.flag_src[j] & TYPE_MASK;
         if ((F && tj == T_GAS) || (E && tj == T_LIQ)) {
           d.flag_dst[j] = (uint8_t)((d.flag_dst[j] & ~TYPE_MASK) | T_IFACE);
-          claim = claim_cell(d, j);
+          if (claim_cell(d, j)) won |= 1u << a;
         }
       }
-      const int pos = wave_append(claim, &d.sc->n_new);
-      if (claim) d.nlist[pos] = (int)j;
     }
+    const int cnt = __popc(won);
+    const int lane = (int)threadIdx.x & 63;
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    const int tot = __shfl(incl, 63, 64);
+    int wbase = 0;
+    if (lane == 0 && tot) wbase = atomicAdd(&d.sc->n_new, tot);
+    int pos = __shfl(wbase, 0, 64) + incl - cnt;
+#pragma unroll
+    for (int a = 1; a < Q; ++a)
+      if ((won >> a) & 1u) d.nlist[pos++] = (int)nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
   }
 }
 };
@@ -1298,15 +1314,15 @@ struct K_volumes {
     unsigned long long *acc = d.b_vacc + (long long)s * SUB * VACC;
     long long w[EX_WORDS] = {0, 0, 0, 0, 0};
     long long cnt = 0;
+    // all words first (independent loads), then clear them
+#pragma unroll
     for (int k = 0; k < SUB; ++k) {
 #pragma unroll
-      for (int c = 0; c < EX_WORDS; ++c) {
-        w[c] += ll(acc[VACC * k + c]);
-        acc[VACC * k + c] = 0;
-      }
+      for (int c = 0; c < EX_WORDS; ++c) w[c] += ll(acc[VACC * k + c]);
       cnt += ll(acc[VACC * k + EX_WORDS]);
-      acc[VACC * k + EX_WORDS] = 0;
     }
+#pragma unroll
+    for (int k = 0; k < SUB * VACC; ++k) acc[k] = 0;
     const ExTerm g = ex_split((double)d.b_ngas[s]);
 #pragma unroll
     for (int c = 0; c < EX_WORDS; ++c) w[c] += g.w[c];
