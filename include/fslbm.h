@@ -167,19 +167,23 @@ int fslbm_bubbles(void *handle, fslbm_bubble *out, int32_t capacity, int32_t *n_
 /* Synchronise and report device-side failures of past steps. */
 int fslbm_sync(void *handle);
 
-/* GPU time per phase of the steps enqueued while timing was enabled,
- * measured with HIP events on the handle's stream (bulk = liquid-cell
+/* GPU time per phase of the sampled steps enqueued while timing was
+ * enabled, measured with HIP events on the handle's stream (bulk = liquid-cell
  * stream-collide kernel, iface = interface kernel, gather includes the
  * per-bubble volume kernel, label = the labelling kernels, which return at
  * once unless a topology change is possible). */
 typedef struct {
   double bulk_ms, iface_ms, convert_ms, excess_ms, gather_ms, label_ms, bubbles_ms;
   double step_ms;   /* sum of the above */
-  int64_t steps;    /* timed steps */
+  int64_t steps;    /* sampled (timed) steps */
 } fslbm_timing;
 
-/* Enable (1) or disable (0) event timing; clears the accumulated times. */
-int fslbm_set_timing(void *handle, int32_t enable);
+/* Event timing of every period-th step enqueued from now on (the first of
+ * them included); period 1 times every step, 0 disables timing.  Each event
+ * delays the next kernel by a few microseconds, so a period well above 1
+ * keeps the timed stream close to an untimed one.  Waits for the handle's
+ * stream and clears the accumulated times.  FSLBM_EINVAL for period < 0. */
+int fslbm_set_timing(void *handle, int32_t period);
 
 /* Synchronise, report the accumulated times and clear them. */
 int fslbm_get_timing(void *handle, fslbm_timing *out);

@@ -221,8 +221,9 @@ def fslbm_destroy(handle) -> None:
     _check(lib().fslbm_destroy(handle))
 
 
-def fslbm_set_timing(handle, enable: bool) -> None:
-    _check(lib().fslbm_set_timing(handle, 1 if enable else 0))
+def fslbm_set_timing(handle, period: int) -> None:
+    """Event timing of every `period`-th step (1: every step, 0: off)."""
+    _check(lib().fslbm_set_timing(handle, int(period)))
 
 
 def fslbm_get_timing(handle) -> dict:

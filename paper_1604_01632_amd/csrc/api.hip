@@ -113,8 +113,10 @@ const char *check_params(const fslbm_params *p) {
 // --------------------------------------------------------------- context
 
 struct Ctx {
-  // per-phase event timing (fslbm_set_timing)
-  bool timing = false;
+  // per-phase event timing (fslbm_set_timing): every timing_period-th
+  // step enqueued since it was set is bracketed by events
+  int timing_period = 0;
+  long long timing_count = 0;
   std::vector<hipEvent_t> events;  // PH_COUNT + 1 per timed step
   size_t used = 0;
   fslbm_params P;
@@ -680,7 +682,7 @@ int fslbm_step(void *handle, int32_t n_steps) {
   Ctx &c = *(Ctx *)handle;
   for (int s = 0; s < n_steps; ++s) {
     const Dev &d = c.dev[c.cur];
-    if (c.timing) {
+    if (c.timing_period > 0 && c.timing_count++ % c.timing_period == 0) {
       while (c.events.size() < c.used + PH_COUNT + 1) {
         hipEvent_t e;
         HIP_TRY(hipEventCreate(&e));
@@ -701,10 +703,13 @@ int fslbm_step(void *handle, int32_t n_steps) {
   return FSLBM_OK;
 }
 
-int fslbm_set_timing(void *handle, int32_t enable) {
+int fslbm_set_timing(void *handle, int32_t period) {
   if (!handle) return fail(FSLBM_EINVAL, "handle is NULL");
+  if (period < 0) return fail(FSLBM_EINVAL, "timing period < 0");
   Ctx &c = *(Ctx *)handle;
-  c.timing = enable != 0;
+  HIP_TRY(hipStreamSynchronize(c.stream));
+  c.timing_period = period;
+  c.timing_count = 0;
   c.used = 0;
   return FSLBM_OK;
 }

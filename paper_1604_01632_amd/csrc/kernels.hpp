@@ -35,6 +35,17 @@ struct Blk {
   int id, n;
 };
 
+// Chunk of a list walked by n blocks of `threads` lanes.  The dispatcher
+// sends block b to XCD b mod 8; the first n chunks are permuted so that the
+// blocks of one XCD take consecutive chunks, and neighbouring interface
+// cells (whose stencils share cache lines) meet in that XCD's L2.  Chunks
+// beyond the first n (lists longer than the grid) keep the identity order.
+__device__ __forceinline__ int xcd_chunk(int c, int m) {
+  if (c >= m) return c;
+  const int q = m >> 3, r = m & 7, x = c & 7;
+  return x * q + (x < r ? x : r) + (c >> 3);
+}
+
 // D3Q19 in the order of the C ABI.
 static constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 static constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
@@ -490,7 +501,10 @@ struct K_geom {
   using R = typename P::R;
   const R *phi = (const R *)d.phi_src;
   const int n = d.sc->n_il_src;
-  for (int k = bk.id * blockDim.x + threadIdx.x; k < n; k += bk.n * blockDim.x) {
+  const int nch = (n + THREADS - 1) / THREADS, m = nch < bk.n ? nch : bk.n;
+  for (int c = bk.id; c < nch; c += bk.n) {
+    const int k = xcd_chunk(c, m) * THREADS + (int)threadIdx.x;
+    if (k >= n) continue;
     const long long i = d.ilist_src[k];
     int x, y, z;
     coords(d, i, x, y, z);
@@ -806,8 +820,9 @@ struct K_iface {
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   Fx mass;
   const int n = d.sc->n_il_src;
-  for (int base = bk.id * blockDim.x; base < n; base += bk.n * blockDim.x) {
-    const int k = base + threadIdx.x;
+  const int nch = (n + THREADS - 1) / THREADS, m = nch < bk.n ? nch : bk.n;
+  for (int c = bk.id; c < nch; c += bk.n) {
+    const int k = xcd_chunk(c, m) * THREADS + (int)threadIdx.x;
     bool cand = false;
     long long i = 0;
     if (k < n) {
@@ -1133,8 +1148,9 @@ struct K_gather {
   using R = typename P::R;
   const int sub = bk.id % SUB;
   const int n = d.sc->n_il_dst;  // interface list of t+1, rebuilt before this kernel
-  for (int base = bk.id * blockDim.x; base < n; base += bk.n * blockDim.x) {
-    const int k = base + threadIdx.x;
+  const int nch = (n + THREADS - 1) / THREADS, m = nch < bk.n ? nch : bk.n;
+  for (int c = bk.id; c < nch; c += bk.n) {
+    const int k = xcd_chunk(c, m) * THREADS + (int)threadIdx.x;
     int key = -1;
     long long v[VACC] = {0, 0, 0, 0, 0, 1};
     if (k < n) {

@@ -189,3 +189,30 @@ def test_invalid_inputs_rejected():
     bid[g] = 77
     with pytest.raises(FslbmError):
         Domain(sc.params(), t, sc.phi, sc.rho, sc.u, bid, sc.bubbles)
+
+
+def test_sampled_phase_timing_leaves_results_unchanged():
+    """Event timing of every k-th step times exactly those steps, rejects a
+    negative period, and does not change what the steps compute."""
+    from paper_1604_01632_amd import Domain, FslbmError, fslbm_get_timing, fslbm_set_timing
+    sc = scenes.config("c1")
+    a = Domain.from_scene(sc, "fp32")
+    b = Domain.from_scene(sc, "fp32")
+    fslbm_set_timing(a.handle, 3)
+    a.step(7)
+    a.step(3)
+    t = fslbm_get_timing(a.handle)
+    assert t["steps"] == 4  # steps 0, 3, 6 and 9 of the ten
+    assert t["bulk_ms"] > 0 and t["step_ms"] >= t["bulk_ms"]
+    fslbm_set_timing(a.handle, 1)
+    a.step(2)
+    assert fslbm_get_timing(a.handle)["steps"] == 2
+    fslbm_set_timing(a.handle, 0)
+    a.step(1)
+    assert fslbm_get_timing(a.handle)["steps"] == 0
+    with pytest.raises(FslbmError):
+        fslbm_set_timing(a.handle, -1)
+    b.step(13)
+    ra, rb = a.read(), b.read()
+    for key in ("cell_type", "bubble_id", "phi", "mass", "f"):
+        assert np.array_equal(ra[key], rb[key]), key
