@@ -70,7 +70,7 @@ Layout make_layout(const fslbm_params &p, const Launchers &L) {
       sz[A_NEWROOTS] = sz[A_NEWSLOT] = B * 4;
   sz[A_BVSTAR] = sz[A_BVOL] = sz[A_BP] = sz[A_BRATIO] = sz[A_BNGAS] = sz[A_BNIFACE] = B * 8;
   sz[A_BVACC] = B * SUB * VACC * 8;
-  sz[A_CACC] = B * NACC * 8;
+  sz[A_CACC] = B * SUB * NACC * 8;
   sz[A_SCALARS] = sizeof(Scalars);
   sz[A_MASSACC] = SUB_MASS * 2 * 8;
   sz[A_BUCKETACC] = SUB * EX_WORDS * 8;
@@ -613,6 +613,14 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
   // zero everything first (not captured in any graph)
   {
     hipError_t e = hipMemsetAsync(c->ws, 0, lay.total, st);
+    if (e != hipSuccess) {
+      fail(FSLBM_EDEVICE, std::string("memset: ") + hipGetErrorString(e));
+      return cleanup_fail(FSLBM_EDEVICE);
+    }
+  }
+  {
+    // labels: -1 outside the labelled set of a step (see k_label_init)
+    hipError_t e = hipMemsetAsync(d.lab, 0xFF, (size_t)N * 4, st);
     if (e != hipSuccess) {
       fail(FSLBM_EDEVICE, std::string("memset: ") + hipGetErrorString(e));
       return cleanup_fail(FSLBM_EDEVICE);

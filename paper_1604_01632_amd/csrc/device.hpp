@@ -96,7 +96,7 @@ struct Dev {
   int32_t *b_rmin, *b_rmax, *b_kept;
   int32_t *b_affect;            // marked by the topology trigger this step
   unsigned long long *b_vacc;   // [B][SUB][VACC]
-  unsigned long long *c_acc;    // [B][NACC] per new component
+  unsigned long long *c_acc;    // [B][SUB][NACC] per new component (zero between runs)
   int32_t *newroots;            // [B]
   int32_t *newslot;             // [B]
   // cell lists: interface cells of t and t+1, conversion candidates, new

@@ -1443,19 +1443,26 @@ __device__ __forceinline__ void uf_union(int32_t *lab, int a, int b) {
 
 // aux2 flags of a root: 1 holds an inlet cell, 2 new component, 4 holds
 // cells of more than one bubble.
+//
+// Labelled set, tile by tile (LTILE consecutive cells, 16 per thread): the
+// cells of the set are listed (one atomic per tile) and labelled with the
+// first cell of their x-run inside the tile.  Cells outside the set hold
+// -1 (filled at creation, restored by k_label_rewrite).
 struct K_label_init {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   __shared__ int wsum[4];
   __shared__ int base_sh;
+  __shared__ int loc[LTILE];
   const int run = d.sc->label_run;
   if (!run) return;
   const bool all = run >= 2;
   const int ntiles = (int)((d.N + LTILE - 1) / LTILE);
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-  // tiles of LTILE cells, 16 consecutive cells per thread
+  const int lb = 16 * (int)threadIdx.x;  // local index of the thread's first cell
   for (int tile = bk.id; tile < ntiles; tile += bk.n) {
-    const long long i0 = (long long)tile * LTILE + 16 * (long long)threadIdx.x;
+    const long long t0 = (long long)tile * LTILE;
+    const long long i0 = t0 + lb;
     uint32_t bits = 0;
     if (i0 < d.N) {
       uint8_t tt[16];
@@ -1472,24 +1479,70 @@ struct K_label_init {
 #pragma unroll
       for (int q = 0; q < 16; ++q)
         if (in_gas_region(tt[q]) && (all || d.b_affect[d.bslot[i0 + q]])) bits |= 1u << q;
-      // initial labels: the first cell of the cell's x-run inside the
-      // 16-cell chunk (a smaller index of the same component), so that a
-      // row segment starts as one tree; -1 outside the set
-      int x = (int)(i0 % d.nx);
-      int start = -1;
-      for (int q = 0; q < 16 && i0 + q < d.N; ++q) {
-        const long long i = i0 + q;
+    }
+    // the whole tile outside the set: nothing to do
+    if (!__syncthreads_or(bits != 0u)) continue;
+    // initial local labels: the first cell of the cell's x-run inside the
+    // tile, so that every row segment starts as a star (depth one).  A run
+    // starts at a set cell that is the tile's first, at x = 0, or after a
+    // cell outside the set; the run that enters a thread's cells from the
+    // left started at the last start of the threads before it (a max-scan
+    // over the block).
+    {
+      __shared__ uint32_t wbits[4];
+      if (lane == 63) wbits[w] = bits;
+      __syncthreads();
+      uint32_t pb = __shfl_up(bits, 1, 64);
+      if (lane == 0) pb = w > 0 ? wbits[w - 1] : 0u;
+      const bool left = threadIdx.x > 0 && ((pb >> 15) & 1u);  // the cell before is set
+      const int x0 = (int)(i0 % d.nx);
+      int last = -1;
+      {
+        int x = x0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const bool prev = q > 0 ? ((bits >> (q - 1)) & 1u) != 0u : left;
+          if (((bits >> q) & 1u) && (x == 0 || !prev)) last = lb + q;
+          if (++x == d.nx) x = 0;
+        }
+      }
+      int incl = last;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off && v > incl) incl = v;
+      }
+      if (lane == 63) wsum[w] = incl;
+      __syncthreads();
+      int carry = __shfl_up(incl, 1, 64);
+      if (lane == 0) carry = -1;
+      for (int k = 0; k < w; ++k) carry = wsum[k] > carry ? wsum[k] : carry;
+      __syncthreads();
+      int start = (left && x0 != 0) ? carry : -1;
+      int x = x0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
         if (x == 0) start = -1;
         if ((bits >> q) & 1u) {
-          if (start < 0) start = (int)i;
-          d.lab[i] = start;
-          d.aux2[i] = 0;
+          if (start < 0) start = lb + q;
+          loc[lb + q] = start;
         } else {
-          d.lab[i] = -1;
+          loc[lb + q] = -1;
           start = -1;
         }
         if (++x == d.nx) x = 0;
       }
+    }
+    __syncthreads();
+    // publish the labels of the set cells (lane-consecutive cells)
+    for (int r = 0; r < LTILE / THREADS; ++r) {
+      const int c = (int)threadIdx.x + THREADS * r;
+      const long long i = t0 + c;
+      if (i >= d.N) break;
+      const int p = loc[c];
+      if (p < 0) continue;
+      d.lab[i] = (int)(t0 + p);
+      d.aux2[i] = 0;
     }
     // list the set cells: one atomic per tile, cell order inside the tile
     const int c = __popc(bits);
@@ -1513,32 +1566,44 @@ struct K_label_init {
       if ((bits >> q) & 1u) d.clist[pos++] = (int)(i0 + q);
     __syncthreads();
   }
-  const long long t0 = (long long)bk.id * blockDim.x + threadIdx.x;
-  for (long long t = t0; t < d.max_bubbles; t += (long long)bk.n * blockDim.x) {
+  const long long g0 = (long long)bk.id * blockDim.x + threadIdx.x;
+  for (long long t = g0; t < d.max_bubbles; t += (long long)bk.n * blockDim.x) {
     d.b_rmin[t] = INT_MAX;
     d.b_rmax[t] = -1;
     // bubbles outside the labelled set keep their entry
     d.b_kept[t] = (!all && d.b_live[t] && !d.b_affect[t]) ? 1 : 0;
-    for (int k = 0; k < NACC; ++k) d.c_acc[t * NACC + k] = 0;
   }
-  if (t0 == 0) d.sc->nnew = 0;
+  if (g0 == 0) d.sc->nnew = 0;
 }
 };
 
+// Every edge of the set (one direction of every opposite pair).
+// Consecutive set cells usually share their label (one x-run) and so do
+// their neighbours in a direction: a lane whose (label, neighbour label)
+// pair equals its left neighbour's skips the union, which the left lane
+// performs (labels only ever move to ancestors, so equal labels, read at
+// any time, mean one tree).
 struct K_label_union {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   if (!d.sc->label_run) return;
-  FSLBM_LABEL_SET(i) {
-    int x, y, z;
-    coords(d, i, x, y, z);
-    // one direction of every opposite pair covers every edge once
+  const int n = d.sc->n_lab;
+  const int lane = (int)threadIdx.x & 63;
+  for (int base = bk.id * (int)blockDim.x; base < n; base += bk.n * (int)blockDim.x) {
+    const int k = base + (int)threadIdx.x;
+    const bool ok = k < n;
+    const long long i = ok ? d.clist[k] : 0;
+    int x = 0, y = 0, z = 0;
+    if (ok) coords(d, i, x, y, z);
+    const int li = ok ? d.lab[i] : -1;
+#pragma unroll
     for (int a = 1; a < Q; a += 2) {
-      const long long j = nbr_checked(d, x, y, z, CX[a], CY[a], CZ[a]);
-      if (j < 0) continue;
-      const int lj = d.lab[j];
-      // outside the set, or already pointing to the same cell (one tree)
-      if (lj < 0 || lj == d.lab[i]) continue;
+      const long long j = ok ? nbr_checked(d, x, y, z, CX[a], CY[a], CZ[a]) : -1;
+      const int lj = j >= 0 ? d.lab[j] : -1;
+      const int pli = __shfl_up(li, 1, 64), plj = __shfl_up(lj, 1, 64);
+      const bool dup = lane > 0 && pli == li && plj == lj;
+      // outside the set, one tree already, or left to the left lane
+      if (lj < 0 || lj == li || dup) continue;
       uf_union(d.lab, (int)i, (int)j);
     }
   }
@@ -1688,7 +1753,7 @@ struct K_label_accumulate {
         v[2 * EX_WORDS + 3] = t == T_INLET ? 1 : 0;
       }
     }
-    wave_add_by_key<NACC>(key, v, d.c_acc, 1, 0);
+    wave_add_by_key<NACC>(key, v, d.c_acc, SUB, bk.id % SUB);
   }
 }
 };
@@ -1705,7 +1770,14 @@ struct K_label_finish {
     if (d.b_live[s] && !d.b_kept[s]) d.b_live[s] = 0;
   __syncthreads();
   for (int k = threadIdx.x; k < nnew; k += blockDim.x) {
-    const unsigned long long *a = d.c_acc + (long long)k * NACC;
+    // the SUB partial sums of the component, cleared for the next run
+    unsigned long long a[NACC];
+    for (int c = 0; c < NACC; ++c) a[c] = 0;
+    unsigned long long *p = d.c_acc + (long long)k * SUB * NACC;
+    for (int u = 0; u < SUB * NACC; ++u) {
+      a[u % NACC] += p[u];
+      p[u] = 0;
+    }
     const int s = d.newslot[k];
     d.b_id[s] = sc->next_id + k;
     long long wv[EX_WORDS], ws[EX_WORDS];
@@ -1732,10 +1804,15 @@ struct K_label_rewrite {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   const Scalars *sc = d.sc;
-  if (!sc->label_run || sc->nnew > d.max_bubbles || sc->nfree < sc->nnew) return;
+  if (!sc->label_run) return;
+  const bool ok = sc->nnew <= d.max_bubbles && sc->nfree >= sc->nnew;
+  // every cell of the set holds its root (k_label_roots); the label is
+  // reset to -1 so that the next labelling finds cells outside its set
+  // without writing the whole field
   FSLBM_LABEL_SET(i) {
     const int r = d.lab[i];
-    if (d.aux2[r] & 2) d.bslot[i] = d.newslot[d.aux0[r]];
+    if (ok && (d.aux2[r] & 2)) d.bslot[i] = d.newslot[d.aux0[r]];
+    d.lab[i] = -1;
   }
 }
 };
