@@ -79,7 +79,7 @@ Layout make_layout(const fslbm_params &p, const Launchers &L) {
   sz[A_GASV] = N * L.real_bytes;
   sz[A_NMASK] = N * 4;
   sz[A_TILECOUNT] = sz[A_TILEOFF] = ((N + 4095) / 4096) * 4;
-  sz[A_FIF] = (size_t)Q * N * L.store_bytes;
+  sz[A_FIF] = N * (((size_t)Q * L.store_bytes + 15) / 16 * 16);  // one padded row per slot
   sz[A_NFLAG] = N;
   sz[A_ISLOT] = N * 4;
   Layout lay;

@@ -95,6 +95,43 @@ __device__ __forceinline__ void st(void *f, int a, long long N, long long i, typ
   ((typename P::S *)f)[a * N + i] = (typename P::S)v;
 }
 
+// Post-collision populations of the interface cells, by list slot: the Q
+// stored values of slot k are contiguous (padded to a multiple of 16
+// bytes), so a cell costs one or two cache lines wherever its slot lies,
+// and moves with 16-byte accesses.
+template <class P>
+struct IfRow {
+  static constexpr int BYTES = (Q * (int)sizeof(typename P::S) + 15) / 16 * 16;
+  static constexpr int WORDS = BYTES / 16;
+  static constexpr int SLOTS = BYTES / (int)sizeof(typename P::S);
+};
+
+template <class P>
+__device__ __forceinline__ void if_load(const void *base, long long k, typename P::R (&f)[Q]) {
+  using S = typename P::S;
+  uint4 w[IfRow<P>::WORDS];
+  const uint4 *p = (const uint4 *)((const char *)base + k * IfRow<P>::BYTES);
+#pragma unroll
+  for (int q = 0; q < IfRow<P>::WORDS; ++q) w[q] = p[q];
+  S v[IfRow<P>::SLOTS];
+  __builtin_memcpy(v, w, sizeof w);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) f[a] = (typename P::R)v[a];
+}
+
+template <class P>
+__device__ __forceinline__ void if_store(void *base, long long k, const typename P::R (&f)[Q]) {
+  using S = typename P::S;
+  S v[IfRow<P>::SLOTS];
+#pragma unroll
+  for (int a = 0; a < IfRow<P>::SLOTS; ++a) v[a] = a < Q ? (S)f[a] : (S)0;
+  uint4 w[IfRow<P>::WORDS];
+  __builtin_memcpy(w, v, sizeof w);
+  uint4 *p = (uint4 *)((char *)base + k * IfRow<P>::BYTES);
+#pragma unroll
+  for (int q = 0; q < IfRow<P>::WORDS; ++q) p[q] = w[q];
+}
+
 // Streaming store of a stored value (non-temporal; half values by their
 // 16-bit pattern).
 template <class P>
@@ -700,8 +737,7 @@ struct K_bulk {
       if (WITH_MASS) mass.add((double)rho, FX_VOL);
     } else if (t == T_IFACE) {
       const int k = d.islot[i];
-#pragma unroll
-      for (int a = 0; a < Q; ++a) f[a] = ld<P>(d.f_if, a, d.N, k);
+      if_load<P>(d.f_if, k, f);
       nfl = d.nflag[k];
     } else {
 #pragma unroll
@@ -795,8 +831,7 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
 
   R rho, u[3];
   collide<P>(d, fin, rho, u);
-#pragma unroll
-  for (int a = 0; a < Q; ++a) st<P>(d.f_if, a, N, k, fin[a]);
+  if_store<P>(d.f_if, k, fin);
   const R phi_new = m_new / rho;
   ((R *)d.mass)[i] = m_new;
   ((R *)d.rhoI)[i] = rho;
