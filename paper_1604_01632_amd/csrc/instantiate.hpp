@@ -56,8 +56,6 @@ static void phase_kernels(int ph, bool with_mass, int bulk_threads, L &&launch) 
       launch.template go<K_label_decide>(G_CELL);
       launch.template go<K_label_assign>(G_ONE);
       launch.template go<K_label_accumulate<P>>(G_CELL);
-      launch.template go<K_label_finish>(G_ONE);
-      launch.template go<K_label_rewrite>(G_CELL);
       break;
     case PH_BUBBLES:
       launch.template go<K_bubbles>(G_ONE);

@@ -1482,7 +1482,7 @@ __device__ __forceinline__ void uf_union(int32_t *lab, int a, int b) {
 // Labelled set, tile by tile (LTILE consecutive cells, 16 per thread): the
 // cells of the set are listed (one atomic per tile) and labelled with the
 // first cell of their x-run inside the tile.  Cells outside the set hold
-// -1 (filled at creation, restored by k_label_rewrite).
+// -1 (filled at creation, restored by k_label_accumulate).
 struct K_label_init {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
@@ -1753,13 +1753,18 @@ struct K_label_assign {
 // Per new component: gas volume V_K = sum (1 - phi) (gas and inlet cells
 // count 1), V*_K = sum over its cells of (V*_b / V_b) times the cell's gas
 // volume (= sum_b V*_b V(b in K) / V_b), cell counts and the inlet flag.
+// Each cell of a new component then moves to the component's slot, and
+// every cell of the set gets its label -1 back (every cell holds its root
+// since k_label_roots), so that the next labelling finds the cells outside
+// its set without writing the whole field.
 template <class P>
 struct K_label_accumulate {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   using R = typename P::R;
   const Scalars *sc = d.sc;
-  if (!sc->label_run || sc->nnew > d.max_bubbles || sc->nfree < sc->nnew) return;
+  if (!sc->label_run) return;
+  const bool ok = sc->nnew <= d.max_bubbles && sc->nfree >= sc->nnew;
   const int n = sc->n_lab;
   for (int base = bk.id * blockDim.x; base < n; base += bk.n * blockDim.x) {
     const int k = base + threadIdx.x;
@@ -1770,7 +1775,7 @@ struct K_label_accumulate {
     if (k < n) {
       const long long i = d.clist[k];
       const int r = d.lab[i];
-      if (d.aux2[r] & 2) {
+      if (ok && (d.aux2[r] & 2)) {
         key = d.aux0[r];
         const uint8_t t = d.flag_dst[i] & TYPE_MASK;
         const double w = t == T_IFACE ? 1.0 - (double)((const R *)d.phi_dst)[i] : 1.0;
@@ -1786,26 +1791,28 @@ struct K_label_accumulate {
         v[2 * EX_WORDS + 1] = (t == T_GAS || t == T_INLET) ? 1 : 0;
         v[2 * EX_WORDS + 2] = t == T_IFACE ? 1 : 0;
         v[2 * EX_WORDS + 3] = t == T_INLET ? 1 : 0;
+        d.bslot[i] = d.newslot[key];
       }
+      d.lab[i] = -1;
     }
     wave_add_by_key<NACC>(key, v, d.c_acc, SUB, bk.id % SUB);
   }
 }
 };
 
-// Single block: install the new bubbles, free the slots of replaced ones.
-struct K_label_finish {
-  static constexpr int THREADS = 1024;
-  static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
+// ------------------------------------------------------------- k_bubbles
+
+// After a labelling run (one block): free the slots of replaced bubbles
+// and install the new components (summing and clearing their partial
+// sums).
+__device__ __forceinline__ void install_new_bubbles(const Dev &d) {
   Scalars *sc = d.sc;
-  if (!sc->label_run || sc->nnew > d.max_bubbles || sc->nfree < sc->nnew) return;
   const int nnew = sc->nnew;
   const int B = d.max_bubbles;
   for (int s = threadIdx.x; s < B; s += blockDim.x)
     if (d.b_live[s] && !d.b_kept[s]) d.b_live[s] = 0;
   __syncthreads();
   for (int k = threadIdx.x; k < nnew; k += blockDim.x) {
-    // the SUB partial sums of the component, cleared for the next run
     unsigned long long a[NACC];
     for (int c = 0; c < NACC; ++c) a[c] = 0;
     unsigned long long *p = d.c_acc + (long long)k * SUB * NACC;
@@ -1833,33 +1840,19 @@ struct K_label_finish {
     if (nnew > 0) sc->n_topology += 1;
   }
 }
-};
 
-struct K_label_rewrite {
-  static constexpr int THREADS = 256;
-  static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
-  const Scalars *sc = d.sc;
-  if (!sc->label_run) return;
-  const bool ok = sc->nnew <= d.max_bubbles && sc->nfree >= sc->nnew;
-  // every cell of the set holds its root (k_label_roots); the label is
-  // reset to -1 so that the next labelling finds cells outside its set
-  // without writing the whole field
-  FSLBM_LABEL_SET(i) {
-    const int r = d.lab[i];
-    if (ok && (d.aux2[r] & 2)) d.bslot[i] = d.newslot[d.aux0[r]];
-    d.lab[i] = -1;
-  }
-}
-};
-
-// ------------------------------------------------------------- k_bubbles
-
-// Single block: gas injection into inlet bubbles and the ideal-gas
-// pressure p = p0 V* / max(V, 1e-2); closes the step.
+// Single block: the new bubbles of a labelling run (unless the table
+// overflowed, which the labelling flagged), gas injection into inlet
+// bubbles and the ideal-gas pressure p = p0 V* / max(V, 1e-2); closes the
+// step.
 struct K_bubbles {
   static constexpr int THREADS = 1024;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   __shared__ int live;
+  const Scalars *sc0 = d.sc;
+  // the same values for every thread of the block
+  if (sc0->label_run && sc0->nnew <= d.max_bubbles && sc0->nfree >= sc0->nnew)
+    install_new_bubbles(d);
   if (threadIdx.x == 0) live = 0;
   __syncthreads();
   for (int s = threadIdx.x; s < d.max_bubbles; s += blockDim.x) {
