@@ -790,28 +790,36 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
   R dm = (R)0;
   bool has_gas = false, has_liq = false;
   const R phi_x = phi[i];
-  // neighbours in three groups of six: the loads of a group (types,
-  // streamed values, fill levels; unused for gas, inlet and wall
-  // neighbours) are issued together, then the rules are applied with
-  // selects; the mass exchange is summed in direction order
+  // the neighbour types first; then, in three groups of six, only the
+  // values a neighbour contributes are fetched (streamed value of liquid
+  // and interface neighbours, fill level of interface neighbours; gas,
+  // inlet and wall neighbours contribute reconstructed or bounced values)
+  // and the rules are applied with selects; the mass exchange is summed in
+  // direction order
+  uint8_t tn[Q];
+#pragma unroll
+  for (int al = 1; al < Q; ++al) tn[al] = d.flag_src[nb.at(d, CX[al], CY[al], CZ[al])] & TYPE_MASK;
 #pragma unroll
   for (int g = 0; g < 3; ++g) {
-    uint8_t ts[6];
     R raw[6], phn[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const int al = 1 + 6 * g + k;
-      const long long s = nb.at(d, CX[al], CY[al], CZ[al]);
-      ts[k] = d.flag_src[s] & TYPE_MASK;
-      raw[k] = ld<P>(d.f_src, opp(al), N, s);
-      phn[k] = phi[s];
+      const uint8_t t = tn[al];
+      raw[k] = (R)0;
+      phn[k] = (R)0;
+      if (t == T_LIQ || t == T_IFACE) {
+        const long long s = nb.at(d, CX[al], CY[al], CZ[al]);
+        raw[k] = ld<P>(d.f_src, opp(al), N, s);
+        if (t == T_IFACE) phn[k] = phi[s];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const int al = 1 + 6 * g + k;
       const int a = opp(al);
       const R recon = gas_pair<P>(rho_gas, drho_gas, ub, a) - fs[al];
-      const uint8_t t = ts[k];
+      const uint8_t t = tn[al];
       const bool gas_src = t == T_GAS || t == T_INLET;
       const bool fluid_src = t == T_LIQ || t == T_IFACE;
       has_gas = has_gas || gas_src;
@@ -848,10 +856,13 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
 }
 
 // Interface cells of time t (list), one per thread; conversion candidates
-// are appended to the candidate list.
+// are appended to the candidate list.  The list of a step is about one
+// round of resident waves, so the FP32/FP16 kernels are held to three waves
+// per SIMD (the FP64 one would spill).
 template <class P, bool WITH_MASS>
 struct K_iface {
   static constexpr int THREADS = 256;
+  static constexpr int MIN_WAVES = P::EXACT ? 1 : 3;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   Fx mass;
   const int n = d.sc->n_il_src;
@@ -1880,8 +1891,19 @@ struct K_bubbles {
 // batch of domains: block b of a batch launch belongs to the domain k with
 // off[k] <= b < off[k + 1] (found by bisection; domains without blocks
 // are skipped).
+// Waves per SIMD a kernel must fit (K::MIN_WAVES where given): bounds the
+// registers of a kernel whose grid is about one round of resident waves.
+template <class K, class = void>
+struct MinWaves {
+  static constexpr int value = 1;
+};
 template <class K>
-__global__ void __launch_bounds__(K::THREADS) k_one(Dev d) {
+struct MinWaves<K, decltype((void)K::MIN_WAVES)> {
+  static constexpr int value = K::MIN_WAVES;
+};
+
+template <class K>
+__global__ void __launch_bounds__(K::THREADS, MinWaves<K>::value) k_one(Dev d) {
   K::run(d, Blk{(int)blockIdx.x, (int)gridDim.x});
 }
 
@@ -1896,7 +1918,8 @@ __device__ __forceinline__ int batch_domain(const int *off, int nd, int b) {
 }
 
 template <class K>
-__global__ void __launch_bounds__(K::THREADS) k_many(const Dev *devs, const int *off, int nd) {
+__global__ void __launch_bounds__(K::THREADS, MinWaves<K>::value) k_many(const Dev *devs, const int *off,
+                                                                         int nd) {
   const int b = (int)blockIdx.x;
   const int k = batch_domain(off, nd, b);
   K::run(devs[k], Blk{b - off[k], off[k + 1] - off[k]});
