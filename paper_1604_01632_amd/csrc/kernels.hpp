@@ -146,6 +146,19 @@ __device__ __forceinline__ void st_stream(void *f, int a, long long N, long long
   }
 }
 
+// Streaming load of a stored value (non-temporal: the old lattice is read
+// once per step).
+template <class P>
+__device__ __forceinline__ typename P::R ld_stream(const void *f, int a, long long N, long long i) {
+  using S = typename P::S;
+  const S *p = (const S *)f + a * N + i;
+  if constexpr (sizeof(S) == 2) {
+    return (typename P::R)__builtin_bit_cast(S, __builtin_nontemporal_load((const unsigned short *)p));
+  } else {
+    return (typename P::R)__builtin_nontemporal_load(p);
+  }
+}
+
 // ------------------------------------------------------------- geometry
 
 // Periodic wrap by adding or subtracting the extent (no integer division;
@@ -716,9 +729,11 @@ struct K_bulk {
         v += CZ[a] == 1 ? szm : (CZ[a] == -1 ? szp : 0);
         return v;
       };
+      // every pulled value is read once in the step: streaming loads keep
+      // the old lattice out of the caches as well
       if (!(fl & NEAR_WALL)) {
 #pragma unroll
-        for (int a = 0; a < Q; ++a) f[a] = ld<P>(d.f_src, a, d.N, src(a));
+        for (int a = 0; a < Q; ++a) f[a] = ld_stream<P>(d.f_src, a, d.N, src(a));
       } else {
         uint8_t ts[Q];
         R own[Q];
@@ -726,7 +741,7 @@ struct K_bulk {
         for (int a = 0; a < Q; ++a) {
           const long long s = src(a);
           ts[a] = d.flag_src[s] & TYPE_MASK;
-          f[a] = ld<P>(d.f_src, a, d.N, s);
+          f[a] = ld_stream<P>(d.f_src, a, d.N, s);
           own[a] = ld<P>(d.f_src, a, d.N, i);
         }
 #pragma unroll
