@@ -1139,51 +1139,58 @@ struct K_excess {
     const long long i = k < nc ? d.clist[k] : d.nlist[k - nc];
     int x, y, z;
     coords(d, i, x, y, z);
+    // the cell's own values and its neighbours' flags of t+1 in one batch
+    // (every rule below uses them; only the gather tags change in this
+    // kernel, so a flag read here stays valid for the type tests)
     const uint8_t t = d.flag_src[i] & TYPE_MASK;
     const uint8_t tn = d.flag_dst[i] & TYPE_MASK;
+    const int slot = d.bslot[i];
+    R *mass = (R *)d.mass;
+    const R m_i = mass[i], rho_i = ((const R *)d.rhoI)[i];
+    uint8_t fn[Q];
+#pragma unroll
+    for (int a = 1; a < Q; ++a) fn[a] = d.flag_dst[nbr(d, x, y, z, CX[a], CY[a], CZ[a])];
     if (t == T_IFACE && (tn == T_LIQ || tn == T_GAS)) {
       const bool filled = tn == T_LIQ;
-      R *mass = (R *)d.mass;
-      const R e = filled ? mass[i] - ((R *)d.rhoI)[i] : mass[i];
+      const R e = filled ? m_i - rho_i : m_i;
       int nI = 0;
 #pragma unroll
       for (int a = 1; a < Q; ++a)
-        if ((d.flag_dst[nbr(d, x, y, z, CX[a], CY[a], CZ[a])] & TYPE_MASK) == T_IFACE) ++nI;
+        if ((fn[a] & TYPE_MASK) == T_IFACE) ++nI;
       if (nI > 0) {
         ((R *)d.excess)[i] = e / (R)nI;
         // tag the receivers
 #pragma unroll
         for (int a = 1; a < Q; ++a) {
-          const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
-          const uint8_t fj = d.flag_dst[j];
-          if ((fj & TYPE_MASK) == T_IFACE && !(fj & GATHER)) d.flag_dst[j] = (uint8_t)(fj | GATHER);
+          if ((fn[a] & TYPE_MASK) == T_IFACE && !(fn[a] & GATHER))
+            d.flag_dst[nbr(d, x, y, z, CX[a], CY[a], CZ[a])] = (uint8_t)(fn[a] | GATHER);
         }
       } else {
         ((R *)d.excess)[i] = (R)0;
         ex_accumulate(orphan, (double)e);
       }
       if (filled) {
-        mass[i] = ((R *)d.rhoI)[i];
+        mass[i] = rho_i;
         ((R *)d.phi_src)[i] = (R)1;
         ((R *)d.phi_dst)[i] = (R)1;
         if (split_possible(d, x, y, z)) {
           trig = true;
-          atomicOr(&d.b_affect[d.bslot[i]], 1);
+          atomicOr(&d.b_affect[slot], 1);
         }
         d.bslot[i] = -1;
       } else {
         mass[i] = (R)0;
         ((R *)d.phi_src)[i] = (R)0;
         ((R *)d.phi_dst)[i] = (R)0;
-        atomicAdd((unsigned long long *)&d.b_ngas[d.bslot[i]], 1ull);
+        atomicAdd((unsigned long long *)&d.b_ngas[slot], 1ull);
       }
     } else if (t == T_LIQ && tn == T_IFACE) {
       // a new gas-region cell: a merge if its gas-region neighbours carry
       // another bubble
-      const int s = d.bslot[i];
+      const int s = slot;
       for (int a = 1; a < Q; ++a) {
         const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
-        if (in_gas_region(d.flag_dst[j] & TYPE_MASK) && d.bslot[j] != s) {
+        if (in_gas_region(fn[a] & TYPE_MASK) && d.bslot[j] != s) {
           trig = true;
           atomicOr(&d.b_affect[s], 1);
           atomicOr(&d.b_affect[d.bslot[j]], 1);
