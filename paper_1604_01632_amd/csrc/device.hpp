@@ -63,7 +63,7 @@ struct Scalars {
   int n_cand;            // conversion candidates of the current step
   int n_new;             // new interface cells of the current step
   int n_lab;             // cells in the labelled set (listed in clist)
-  int pad_;
+  int n_roots;           // components of the labelled set (roots listed in nlist)
 };
 constexpr int ERR_CAPACITY = 1;
 constexpr int ERR_NONFINITE = 2;

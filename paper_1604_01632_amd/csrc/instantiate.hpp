@@ -53,7 +53,6 @@ static void phase_kernels(int ph, bool with_mass, int bulk_threads, L &&launch) 
       launch.template go<K_label_init>(G_CELL);
       launch.template go<K_label_union>(G_CELL);
       launch.template go<K_label_roots>(G_CELL);
-      launch.template go<K_label_decide>(G_CELL);
       launch.template go<K_label_assign>(G_ONE);
       launch.template go<K_label_accumulate<P>>(G_CELL);
       break;

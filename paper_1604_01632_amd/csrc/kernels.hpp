@@ -1445,6 +1445,7 @@ struct K_volumes {
     sc->n_cand = 0;
     sc->n_new = 0;
     sc->n_lab = 0;
+    sc->n_roots = 0;
     if (d.force_topology) sc->label_run = 2;
   }
 }
@@ -1698,6 +1699,9 @@ struct K_label_roots {
     if (r == (int)i) {
       atomicMin(&d.b_rmin[s], r);
       atomicMax(&d.b_rmax[s], r);
+      // the roots are listed (the new-cell list is free during labelling)
+      const int q = atomicAdd(&d.sc->n_roots, 1);
+      if (q < (int)d.N) d.nlist[q] = r;
     }
     if ((d.flag_dst[i] & TYPE_MASK) == T_INLET) atomicOr(&d.aux2[r], 1);
     int x, y, z;
@@ -1717,37 +1721,38 @@ struct K_label_roots {
 }
 };
 
-// A component keeps its bubble if it holds exactly one bubble and that
-// bubble lies in no other component; every other component is new.
-struct K_label_decide {
-  static constexpr int THREADS = 256;
-  static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
-  if (!d.sc->label_run) return;
-  FSLBM_LABEL_SET(i) {
-    if (d.lab[i] != (int)i) continue;
-    const int s = d.bslot[i];
-    const bool single = !(d.aux2[i] & 4) && d.b_rmin[s] == (int)i && d.b_rmax[s] == (int)i;
-    if (single) {
-      d.b_kept[s] = 1;
-    } else {
-      const int k = atomicAdd(&d.sc->nnew, 1);
-      if (k < d.max_bubbles) d.newroots[k] = (int)i;
-      atomicOr(&d.aux2[i], 2);
-    }
-  }
-}
-};
-
-// Single block: order the new components by their smallest cell index,
-// give each the next fresh ID and a free slot, and fix the V* ratio of
-// every old bubble.
+// Single block: decide, per listed root, whether its component keeps its
+// bubble; order the new components by their smallest cell index, give each
+// the next fresh ID and a free slot, and fix the V* ratio of every old
+// bubble.
 struct K_label_assign {
   static constexpr int THREADS = 1024;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   if (!d.sc->label_run) return;
   Scalars *sc = d.sc;
   const int B = d.max_bubbles;
-  const int nnew = sc->nnew;
+  __shared__ int s_nnew;
+  if (threadIdx.x == 0) s_nnew = 0;
+  __syncthreads();
+  // over the listed roots: a component keeps its bubble if it holds
+  // exactly one bubble and that bubble lies in no other component; every
+  // other component is new
+  const int nr = sc->n_roots;
+  for (int k = threadIdx.x; k < nr; k += blockDim.x) {
+    const int r = d.nlist[k];
+    const int s = d.bslot[r];
+    const bool single = !(d.aux2[r] & 4) && d.b_rmin[s] == r && d.b_rmax[s] == r;
+    if (single) {
+      d.b_kept[s] = 1;
+    } else {
+      const int q = atomicAdd(&s_nnew, 1);
+      if (q < B) d.newroots[q] = r;
+      atomicOr(&d.aux2[r], 2);
+    }
+  }
+  __syncthreads();
+  const int nnew = s_nnew;
+  if (threadIdx.x == 0) sc->nnew = nnew;
   if (nnew > B) {
     if (threadIdx.x == 0) sc->err |= ERR_CAPACITY;
     return;
