@@ -169,10 +169,11 @@ int fslbm_sync(void *handle);
 
 /* GPU time per phase of the sampled steps enqueued while timing was
  * enabled, measured with HIP events on the handle's stream (bulk = liquid-cell
- * stream-collide kernel, iface = interface kernel, gather includes the
- * per-bubble volume kernel, label = the labelling kernels, which return at
- * once unless a topology change is possible, bubbles = installing the new
- * bubbles of a labelling run and the pressure update). */
+ * stream-collide kernel, iface = geometry and interface kernels, gather =
+ * interface-list rebuild and excess gather, label = per-bubble volume sums
+ * (every step) and the labelling kernels, which return at once unless a
+ * topology change is possible, bubbles = installing the new bubbles of a
+ * labelling run and the pressure update). */
 typedef struct {
   double bulk_ms, iface_ms, convert_ms, excess_ms, gather_ms, label_ms, bubbles_ms;
   double step_ms;   /* sum of the above */

@@ -47,7 +47,6 @@ static void phase_kernels(int ph, bool with_mass, int bulk_threads, L &&launch) 
       launch.template go<K_list_scan>(G_ONE);
       launch.template go<K_list_fill>(G_TILE);
       launch.template go<K_gather<P>>(G_LIST);
-      launch.template go<K_volumes<P>>(G_ONE);
       break;
     case PH_LABEL:
       launch.template go<K_label_init>(G_CELL);

@@ -14,11 +14,13 @@
 //   k_excess      excess mass of converted cells, bucket, topology trigger
 //   k_gather      interface cells of t+1 pull excess mass; fill levels;
 //                 per-bubble volume sums (Sec. 2.3); next interface list
-//   k_volumes     per-bubble volumes, bucket share, total mass
-//   k_label_*     union-find labelling of the gas region and the merge /
-//                 split rules (Sec. 2.3.1, 2.3.2) - every kernel returns at
-//                 once unless the trigger fired
-//   k_bubbles     injection and ideal-gas pressure (Sec. 2.2)
+//   k_label_*     per-bubble volumes, bucket share and total mass (at the
+//                 start of k_label_init, every step); union-find labelling
+//                 of the gas region and the merge / split rules
+//                 (Sec. 2.3.1, 2.3.2) - the labelling returns at once
+//                 unless the trigger fired
+//   k_bubbles     new bubbles of a labelling run, injection and ideal-gas
+//                 pressure (Sec. 2.2); the list counters of the next step
 #pragma once
 #include <float.h>
 #include <limits.h>
@@ -1199,6 +1201,8 @@ struct K_excess {
     }
   }
   if (trig) atomicMax(&d.sc->label_run, 1);
+  // a forced topology pass labels the whole gas region every step
+  if (d.force_topology && bk.id == 0 && threadIdx.x == 0) atomicMax(&d.sc->label_run, 2);
   block_ex_add(orphan, d.bucket_acc, bk.id % SUB);
 }
 };
@@ -1371,31 +1375,18 @@ struct K_list_fill {
 }
 };
 
-// ------------------------------------------------------------- k_volumes
+// ------------------------------------------------------- bubble volumes
 
 // Per-bubble volume V = (gas + inlet cells) + sum over interface cells of
-// (1 - phi), exactly rounded; orphan bucket; total mass.
-template <class P>
-struct K_volumes {
-  static constexpr int THREADS = 1024;
-  static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
-  __shared__ long long red[1024 / 64][2];
-  // total mass diagnostic: block reduction of the replicated slots
-  long long mh = 0, ml = 0;
-  for (int k = threadIdx.x; k < SUB_MASS; k += blockDim.x) {
-    mh += ll(d.mass_acc[2 * k]);
-    ml += ll(d.mass_acc[2 * k + 1]);
-    d.mass_acc[2 * k] = d.mass_acc[2 * k + 1] = 0;
-  }
-  mh = wave_sum(mh);
-  ml = wave_sum(ml);
-  if (threadIdx.x % 64 == 0) {
-    red[threadIdx.x / 64][0] = mh;
-    red[threadIdx.x / 64][1] = ml;
-  }
-  for (int s = threadIdx.x; s < d.max_bubbles; s += blockDim.x) {
+// (1 - phi), exactly rounded (one thread per bubble slot over the whole
+// grid); orphan bucket and total mass (block 0).  Runs at the start of the
+// first labelling kernel, every step.
+__device__ __forceinline__ void bubble_volumes(const Dev &d, Blk bk) {
+  __shared__ long long red[4][2];
+  const long long g0 = (long long)bk.id * blockDim.x + threadIdx.x;
+  for (long long s = g0; s < d.max_bubbles; s += (long long)bk.n * blockDim.x) {
     if (!d.b_live[s]) continue;
-    unsigned long long *acc = d.b_vacc + (long long)s * SUB * VACC;
+    unsigned long long *acc = d.b_vacc + s * SUB * VACC;
     long long w[EX_WORDS] = {0, 0, 0, 0, 0};
     long long cnt = 0;
     // all words first (independent loads), then clear them
@@ -1412,6 +1403,20 @@ struct K_volumes {
     for (int c = 0; c < EX_WORDS; ++c) w[c] += g.w[c];
     d.b_vol[s] = ex_value(w);
     d.b_niface[s] = cnt;
+  }
+  if (bk.id != 0) return;  // uniform per block
+  // total mass diagnostic: block reduction of the replicated slots
+  long long mh = 0, ml = 0;
+  for (int k = threadIdx.x; k < SUB_MASS; k += blockDim.x) {
+    mh += ll(d.mass_acc[2 * k]);
+    ml += ll(d.mass_acc[2 * k + 1]);
+    d.mass_acc[2 * k] = d.mass_acc[2 * k + 1] = 0;
+  }
+  mh = wave_sum(mh);
+  ml = wave_sum(ml);
+  if (threadIdx.x % 64 == 0) {
+    red[threadIdx.x / 64][0] = mh;
+    red[threadIdx.x / 64][1] = ml;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1440,16 +1445,8 @@ struct K_volumes {
     sc->bucket = bucket;
     sc->n_iface = nI;
     sc->share = nI > 0 ? bucket / (double)nI : 0.0;
-    sc->n_il_src = sc->n_il_dst;
-    sc->n_il_dst = 0;
-    sc->n_cand = 0;
-    sc->n_new = 0;
-    sc->n_lab = 0;
-    sc->n_roots = 0;
-    if (d.force_topology) sc->label_run = 2;
   }
 }
-};
 
 // ---------------------------------------------------------- labelling
 
@@ -1523,6 +1520,7 @@ struct K_label_init {
   __shared__ int wsum[4];
   __shared__ int base_sh;
   __shared__ int loc[LTILE];
+  bubble_volumes(d, bk);
   const int run = d.sc->label_run;
   if (!run) return;
   const bool all = run >= 2;
@@ -1906,6 +1904,13 @@ struct K_bubbles {
     Scalars *sc = d.sc;
     sc->n_live = live;
     sc->label_run = 0;
+    // the lists of the next step
+    sc->n_il_src = sc->n_il_dst;
+    sc->n_il_dst = 0;
+    sc->n_cand = 0;
+    sc->n_new = 0;
+    sc->n_lab = 0;
+    sc->n_roots = 0;
     sc->step += 1;
     if (!isfinite(sc->total_mass)) sc->err |= ERR_NONFINITE;
   }
