@@ -105,3 +105,29 @@ def test_batch_rejects_bad_input():
         Batch([a, c])
     with pytest.raises(FslbmError):
         Batch([a, a])
+
+
+@pytest.mark.parametrize("case", ["thread_64x64x256", "orifice_48x48x96"])
+def test_larger_domain_alone_equals_batch_of_one(case):
+    """A domain stepped on its own and the same domain in a batch of one
+    (graph launches of the batched kernels) give the same state bit for
+    bit over many steps of a larger scene, checked twice along the way:
+    a thread rupture with its conversions and labelling runs, and a walled,
+    non-periodic box with an inlet."""
+    from paper_1604_01632_amd import Batch, Domain
+
+    if case.startswith("thread"):
+        sc, steps = scenes.config("c2"), (700, 800)
+    else:
+        sc, steps = scenes.orifice(n=(48, 48, 96), r=5.0, g=1e-5, Q=0.05), (300, 300)
+    alone = Domain.from_scene(sc, "fp32")
+    other = Domain.from_scene(sc, "fp32")
+    b = Batch([other], tuning_cache_path="")
+    done = 0
+    for n in steps:
+        alone.step(n)
+        b.step(n)
+        done += n
+        say(f"[alone-vs-batch] {case}: {done} steps, bubbles {len(alone.bubbles()['id'])}")
+        _same(alone, other, f"{case} after {done} steps")
+    b.close()
