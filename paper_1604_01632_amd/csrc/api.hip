@@ -48,7 +48,7 @@ enum Arr {
   A_AUX0, A_AUX2, A_BID, A_BFLAGS, A_BLIVE, A_BRMIN, A_BRMAX, A_BKEPT, A_BAFFECT, A_NEWROOTS,
   A_NEWSLOT, A_BVSTAR, A_BVOL, A_BP, A_BRATIO, A_BNGAS, A_BNIFACE, A_BVACC, A_CACC,
   A_SCALARS, A_MASSACC, A_BUCKETACC, A_ILIST0, A_ILIST1, A_CLIST, A_NLIST, A_MARK, A_GASV, A_NMASK, A_TILECOUNT, A_TILEOFF,
-  A_FIF, A_NFLAG, A_ISLOT, A_COUNT
+  A_FIF0, A_FIF1, A_NFLAG, A_ISLOT0, A_ISLOT1, A_COUNT
 };
 
 struct Layout {
@@ -79,9 +79,9 @@ Layout make_layout(const fslbm_params &p, const Launchers &L) {
   sz[A_GASV] = N * L.real_bytes;
   sz[A_NMASK] = N * 4;
   sz[A_TILECOUNT] = sz[A_TILEOFF] = ((N + 4095) / 4096) * 4;
-  sz[A_FIF] = N * (((size_t)Q * L.store_bytes + 15) / 16 * 16);  // one padded row per slot
+  sz[A_FIF0] = sz[A_FIF1] = N * (((size_t)Q * L.store_bytes + 15) / 16 * 16);  // one padded row per slot
   sz[A_NFLAG] = N;
-  sz[A_ISLOT] = N * 4;
+  sz[A_ISLOT0] = sz[A_ISLOT1] = N * 4;
   Layout lay;
   size_t o = 0;
   for (int k = 0; k < A_COUNT; ++k) {
@@ -190,9 +190,7 @@ void build_devs(Ctx &c) {
   d.nmask = at<uint32_t>(ws, lay, A_NMASK);
   d.tilecount = at<int32_t>(ws, lay, A_TILECOUNT);
   d.tileoff = at<int32_t>(ws, lay, A_TILEOFF);
-  d.f_if = ws + lay.off[A_FIF];
   d.nflag = at<uint8_t>(ws, lay, A_NFLAG);
-  d.islot = at<int32_t>(ws, lay, A_ISLOT);
   for (int s = 0; s < 2; ++s) {
     Dev e = d;
     e.f_src = ws + lay.off[s == 0 ? A_F0 : A_F1];
@@ -203,6 +201,10 @@ void build_devs(Ctx &c) {
     e.phi_dst = ws + lay.off[s == 0 ? A_PHI1 : A_PHI0];
     e.ilist_src = at<int32_t>(ws, lay, s == 0 ? A_ILIST0 : A_ILIST1);
     e.ilist_dst = at<int32_t>(ws, lay, s == 0 ? A_ILIST1 : A_ILIST0);
+    e.f_if = ws + lay.off[s == 0 ? A_FIF0 : A_FIF1];
+    e.f_if_prev = ws + lay.off[s == 0 ? A_FIF1 : A_FIF0];
+    e.islot = at<int32_t>(ws, lay, s == 0 ? A_ISLOT0 : A_ISLOT1);
+    e.islot_alt = at<int32_t>(ws, lay, s == 0 ? A_ISLOT1 : A_ISLOT0);
     c.dev[s] = e;
   }
 }

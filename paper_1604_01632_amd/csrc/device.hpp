@@ -64,6 +64,8 @@ struct Scalars {
   int n_new;             // new interface cells of the current step
   int n_lab;             // cells in the labelled set (listed in clist)
   int n_roots;           // components of the labelled set (roots listed in nlist)
+  int if_prev;           // the interface rows of the previous step are valid
+  int pad_;
 };
 constexpr int ERR_CAPACITY = 1;
 constexpr int ERR_NONFINITE = 2;
@@ -111,10 +113,14 @@ struct Dev {
   int32_t *tilecount, *tileoff;
   // outputs of the interface kernel by list slot (post-collision values,
   // new flag byte), merged into the lattice by the liquid-cell kernel, and
-  // the list slot of every interface cell of time t
+  // the list slot of every interface cell of time t.  Rows and slots are
+  // kept for two steps (by step parity): the interface kernel reads the
+  // rows of the previous step for the cells that were interface cells then
   void *f_if;
+  const void *f_if_prev;
   uint8_t *nflag;
   int32_t *islot;
+  int32_t *islot_alt;  // slots of the list of t-1, until k_list_fill writes those of t+1
   // scalars and global accumulators
   Scalars *sc;
   unsigned long long *mass_acc;   // [SUB_MASS][2]

@@ -790,9 +790,17 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
   const R rho_gas = P::EXACT ? g : (R)1 + g;
   const R drho_gas = P::EXACT ? g - (R)1 : g;
 
+  // the cell's own post-collision values: from its row of the previous
+  // step if it was an interface cell then (the lattice holds a copy of
+  // that row: one or two cache lines instead of one per direction), else
+  // from the lattice.  The destination flags still hold the types of t-1.
   R fs[Q];
+  if (d.sc->if_prev && (d.flag_dst[i] & TYPE_MASK) == T_IFACE) {
+    if_load<P>(d.f_if_prev, d.islot_alt[i], fs);
+  } else {
 #pragma unroll
-  for (int a = 0; a < Q; ++a) fs[a] = ld<P>(d.f_src, a, N, i);
+    for (int a = 0; a < Q; ++a) fs[a] = ld<P>(d.f_src, a, N, i);
+  }
   R ub[3];
   {
     R r, dr;
@@ -1368,7 +1376,7 @@ struct K_list_fill {
     if ((bits >> b) & 1u) {
       const long long i = i0 + b;
       d.ilist_dst[pos] = (int)i;
-      d.islot[i] = pos;
+      d.islot_alt[i] = pos;  // the slots of the next step
       ++pos;
     }
   }
@@ -1911,6 +1919,7 @@ struct K_bubbles {
     sc->n_new = 0;
     sc->n_lab = 0;
     sc->n_roots = 0;
+    sc->if_prev = 1;  // the interface rows of this step serve the next one
     sc->step += 1;
     if (!isfinite(sc->total_mass)) sc->err |= ERR_NONFINITE;
   }
