@@ -1467,8 +1467,13 @@ __device__ __forceinline__ void bubble_volumes(const Dev &d, Blk bk) {
 // on the first step and when labelling is forced): a bubble the trigger did
 // not mark has lost no cell and touched no other bubble, so it is still one
 // component holding no other bubble and keeps its ID.
+// Label reads may see an older value through the caches: an older label
+// is still an ancestor (labels only move up their tree and are always
+// smaller than the cell), so every walk ends at a cell of the same tree,
+// and the linking atomics below act on the current value and retry.  Reads
+// with workgroup scope stay in the caches instead of going to memory.
 __device__ __forceinline__ int lab_load(const int32_t *lab, long long i) {
-  return __hip_atomic_load(&lab[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(&lab[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Find with path halving: every visited cell is re-pointed to its
