@@ -188,6 +188,97 @@ def bench_batched(args) -> int:
     return 0
 
 
+def _bubble_errors(ref: dict, got: dict) -> dict:
+    """Bubble count of `got` against `ref` and the largest relative volume
+    error, bubbles matched by ID when both tables hold the same IDs, else by
+    volume rank."""
+    same_ids = ref["id"].tolist() == got["id"].tolist()
+    if same_ids:
+        rv, gv = np.asarray(ref["volume"]), np.asarray(got["volume"])
+    else:
+        rv, gv = np.sort(ref["volume"])[::-1], np.sort(got["volume"])[::-1]
+        k = min(len(rv), len(gv))
+        rv, gv = rv[:k], gv[:k]
+    err = float(np.max(np.abs(gv - rv) / np.abs(rv))) if len(rv) else 0.0
+    return {"bubbles": int(len(got["id"])), "bubbles_fp64": int(len(ref["id"])),
+            "same_ids": bool(same_ids), "max_rel_volume_error": err}
+
+
+def bench_forms(args) -> int:
+    """Precision forms against the plain FP64 form on the same GPU: the
+    256^3 thread workload stepped in FP64, FP32 and FP16-deviation storage
+    (MLUPS of each), and the accuracy of FP32 and FP16-deviation against
+    FP64 at the horizons of the thread-rupture (C2, 20000 steps) and orifice
+    (C3, 50000 steps) scenes: bubble count, per-bubble volume, total-mass
+    drift.  The FP64 path reproduces the oracle bit for bit on the parity
+    cases; at these horizons it stands in for the oracle, whose CPU run
+    would take hours."""
+    import torch
+
+    import paper_1604_01632_amd as F
+    import scenes
+
+    torch.cuda.set_device(0)
+    forms = ("fp64", "fp32", "fp16dev")
+    sc = scenes.config("p1")
+    speed = {}
+    for prec in forms:
+        dom = F.Domain.from_scene(sc, prec)
+        dom.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dom.step(args.steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        speed[prec] = {"mlups": round(sc.n * args.steps / dt / 1e6, 1),
+                       "ms_per_step": round(dt / args.steps * 1e3, 4)}
+        log(f"[bench] p1 {prec}: {speed[prec]}")
+        dom.close()
+        del dom
+        torch.cuda.empty_cache()
+    accuracy = {}
+    for name, horizon in (("c2", args.c2_steps), ("c3", args.c3_steps)):
+        cs = scenes.config(name)
+        res = {}
+        for prec in forms:
+            dom = F.Domain.from_scene(cs, prec)
+            m0 = dom.read(("cell_type",))["scalars"]["total_mass"]
+            done = 0
+            while done < horizon:
+                n = min(5000, horizon - done)
+                dom.step(n)
+                dom.sync()
+                done += n
+                log(f"[bench] {name} {prec}: {done}/{horizon} steps")
+            s = dom.read(("cell_type",))["scalars"]
+            res[prec] = (dom.bubbles(), abs(s["total_mass"] - m0) / m0)
+            dom.close()
+            del dom
+            torch.cuda.empty_cache()
+        accuracy[name] = {"horizon": horizon, "fp64_mass_drift": res["fp64"][1]}
+        for prec in ("fp32", "fp16dev"):
+            e = _bubble_errors(res["fp64"][0], res[prec][0])
+            e["mass_drift"] = res[prec][1]
+            accuracy[name][prec] = e
+        log(f"[bench] {name}: {accuracy[name]}")
+    out = {
+        "metric": METRIC, "value": speed["fp32"]["mlups"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": speed["fp32"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "precision forms: p1 256^3 thread rupture in fp64, fp32 and "
+                               "fp16-deviation storage (value: fp32); accuracy of fp32 and "
+                               "fp16dev against fp64 at the c2 and c3 horizons",
+                   "p1": speed,
+                   "speedup_vs_fp64": {p: round(speed[p]["mlups"] / speed["fp64"]["mlups"], 2)
+                                       for p in forms},
+                   "accuracy": accuracy},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_served(args) -> int:
     """Served form: a Poisson stream of foam requests at 80 % of the measured
     capacity, continuous batching against the plain first-come-first-served
@@ -259,7 +350,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="p1",
-                    help="p1 (default: 256^3 thread rupture), c1/c2/c3, batched, served")
+                    help="p1 (default: 256^3 thread rupture), c1/c2/c3, batched, served, forms")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16dev"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -278,6 +369,8 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=48, help="served workload: requests")
     ap.add_argument("--max-active", type=int, default=64, help="served workload: slots")
     ap.add_argument("--quantum", type=int, default=100, help="served workload: steps per decision")
+    ap.add_argument("--c2-steps", type=int, default=20000, help="forms workload: c2 horizon")
+    ap.add_argument("--c3-steps", type=int, default=50000, help="forms workload: c3 horizon")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -290,6 +383,8 @@ def main() -> int:
         return bench_batched(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload == "forms":
+        return bench_forms(args)
 
     import numpy as np
     import torch

@@ -70,6 +70,35 @@ constexpr double TIE_REL = 1e-10;
 // from the lattice weights are stored (float / half) and all arithmetic is
 // done on them in float, so that the weights (which do not sum to one in
 // float) never enter a rounded sum and mass is not biased.
+// Random 32 bits for a (cell, salt) pair: lowbias32 finaliser
+// (xorshift-multiply, C. Wellons) of the cell mixed with the salt.
+__device__ __forceinline__ uint32_t store_key(long long i, uint32_t salt) {
+  uint32_t x = (uint32_t)i ^ (salt * 0x9E3779B9u);
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// x rounded to one of its two neighbouring half values, away from zero
+// with probability (|x| - lo) / (hi - lo): unbiased in expectation.  With s
+// the half spacing at |x| (2^(e-10) for exponent e, at least 2^-24), the
+// result is floor(|x| / s + u) s for u uniform in [0, 1): the scalings are
+// exact powers of two and the result is a half value, so the conversion is
+// exact.
+__device__ __forceinline__ _Float16 half_stochastic(float x, uint32_t r) {
+  const uint32_t ab = __float_as_uint(x) & 0x7fffffffu;
+  int e = (int)(ab >> 23) - 127;
+  e = e < -14 ? -14 : e;
+  const float s = __uint_as_float((uint32_t)(e - 10 + 127) << 23);
+  const float inv = __uint_as_float((uint32_t)(10 - e + 127) << 23);
+  const float u = (float)(r >> 8) * 0x1p-24f;
+  const float y = floorf(__uint_as_float(ab) * inv + u) * s;
+  return (_Float16)copysignf(y, x);
+}
+
 struct P64 {
   using S = double;
   using R = double;
@@ -81,10 +110,35 @@ struct P32 {
   static constexpr bool EXACT = false;
 };
 struct P16 {
-  using S = _Float16;  // round to nearest even on store
+  using S = _Float16;  // see to_store
   using R = float;
   static constexpr bool EXACT = false;
 };
+
+// The stored values of one cell's new populations.  FP64 and FP32 store
+// them as computed.  FP16 rounds the moving populations to nearest and
+// gives their rounding residues (exact in float) to the rest population,
+// which is rounded stochastically (key: random bits of the cell and step).
+// Rounding every deviation to nearest would add the same error to every
+// cell of a near-uniform region, step after step, and drift the mass; this
+// way a stored cell keeps its deviation sum up to one unbiased rounding.
+template <class P>
+__device__ __forceinline__ void to_store(const typename P::R (&f)[Q], typename P::S (&out)[Q],
+                                         uint32_t key) {
+  using S = typename P::S;
+  if constexpr (sizeof(S) == 2) {
+    float res = 0.0f;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      out[a] = (S)f[a];
+      res += f[a] - (float)out[a];
+    }
+    out[0] = half_stochastic(f[0] + res, key);
+  } else {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) out[a] = (S)f[a];
+  }
+}
 
 // Stored value of direction a at cell i: f (FP64) or h = f - w (others).
 template <class P>
@@ -92,9 +146,10 @@ __device__ __forceinline__ typename P::R ld(const void *f, int a, long long N, l
   return (typename P::R)((const typename P::S *)f)[a * N + i];
 }
 
+// A stored value (exact conversion, or the value of to_store).
 template <class P>
-__device__ __forceinline__ void st(void *f, int a, long long N, long long i, typename P::R v) {
-  ((typename P::S *)f)[a * N + i] = (typename P::S)v;
+__device__ __forceinline__ void st(void *f, int a, long long N, long long i, typename P::S v) {
+  ((typename P::S *)f)[a * N + i] = v;
 }
 
 // Post-collision populations of the interface cells, by list slot: the Q
@@ -122,11 +177,11 @@ __device__ __forceinline__ void if_load(const void *base, long long k, typename 
 }
 
 template <class P>
-__device__ __forceinline__ void if_store(void *base, long long k, const typename P::R (&f)[Q]) {
+__device__ __forceinline__ void if_store(void *base, long long k, const typename P::S (&f)[Q]) {
   using S = typename P::S;
   S v[IfRow<P>::SLOTS];
 #pragma unroll
-  for (int a = 0; a < IfRow<P>::SLOTS; ++a) v[a] = a < Q ? (S)f[a] : (S)0;
+  for (int a = 0; a < IfRow<P>::SLOTS; ++a) v[a] = a < Q ? f[a] : (S)0;
   uint4 w[IfRow<P>::WORDS];
   __builtin_memcpy(w, v, sizeof w);
   uint4 *p = (uint4 *)((char *)base + k * IfRow<P>::BYTES);
@@ -138,13 +193,13 @@ __device__ __forceinline__ void if_store(void *base, long long k, const typename
 // 16-bit pattern).
 template <class P>
 __device__ __forceinline__ void st_stream(void *f, int a, long long N, long long i,
-                                          typename P::R v) {
+                                          typename P::S sv) {
   using S = typename P::S;
   S *p = (S *)f + a * N + i;
   if constexpr (sizeof(S) == 2) {
-    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, (S)v), (unsigned short *)p);
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, sv), (unsigned short *)p);
   } else {
-    __builtin_nontemporal_store((S)v, p);
+    __builtin_nontemporal_store(sv, p);
   }
 }
 
@@ -760,11 +815,20 @@ struct K_bulk {
 #pragma unroll
       for (int a = 0; a < Q; ++a) f[a] = (R)0;
     }
+    // stored values: the collided populations of a liquid cell through
+    // to_store, exact copies (interface rows, zeros) otherwise
+    typename P::S sv[Q];
+    if (t == T_LIQ) {
+      to_store<P>(f, sv, store_key(i, (uint32_t)d.sc->step));
+    } else {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) sv[a] = (typename P::S)f[a];
+    }
     // the new lattice is written once and read only in the next step:
     // non-temporal stores keep it from evicting the interface data that the
     // following kernels read from the caches
 #pragma unroll
-    for (int a = 0; a < Q; ++a) st_stream<P>(d.f_dst, a, d.N, i, f[a]);
+    for (int a = 0; a < Q; ++a) st_stream<P>(d.f_dst, a, d.N, i, sv[a]);
     d.flag_dst[i] = nfl;
   } else if (in) {
     d.flag_dst[i] = fl & (STATIC_BITS | TYPE_MASK);
@@ -864,7 +928,11 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
 
   R rho, u[3];
   collide<P>(d, fin, rho, u);
-  if_store<P>(d.f_if, k, fin);
+  {
+    typename P::S sv[Q];
+    to_store<P>(fin, sv, store_key(i, (uint32_t)d.sc->step));
+    if_store<P>(d.f_if, k, sv);
+  }
   const R phi_new = m_new / rho;
   ((R *)d.mass)[i] = m_new;
   ((R *)d.rhoI)[i] = rho;
@@ -1064,8 +1132,12 @@ struct K_conv_init {
         const R ubar[3] = {us[0] / (R)cnt, us[1] / (R)cnt, us[2] / (R)cnt};
         R fe[Q];
         eqv<P>(rb, P::EXACT ? rb - (R)1 : mean, ubar, fe);
+        {
+          typename P::S sv[Q];
+          to_store<P>(fe, sv, store_key(i, (uint32_t)d.sc->step));
 #pragma unroll
-        for (int c = 0; c < Q; ++c) st<P>(d.f_dst, c, d.N, i, fe[c]);
+          for (int c = 0; c < Q; ++c) st<P>(d.f_dst, c, d.N, i, sv[c]);
+        }
         ((R *)d.rhoI)[i] = rb;
         ((R *)d.mass)[i] = (R)0;
         atomicAdd((unsigned long long *)&d.b_ngas[d.bslot[i]], (unsigned long long)-1ll);
@@ -1988,7 +2060,11 @@ __global__ void __launch_bounds__(256) k_init_feq(Dev d, const double *rho, cons
     } else {
       for (int a = 0; a < Q; ++a) fe[a] = wgt(a);
     }
-    for (int a = 0; a < Q; ++a) st<P>(d.f_src, a, d.N, i, (R)(P::EXACT ? fe[a] : fe[a] - wgt(a)));
+    R fr[Q];
+    for (int a = 0; a < Q; ++a) fr[a] = (R)(P::EXACT ? fe[a] : fe[a] - wgt(a));
+    typename P::S sv[Q];
+    to_store<P>(fr, sv, store_key(i, 0xFFFFFFFFu));
+    for (int a = 0; a < Q; ++a) st<P>(d.f_src, a, d.N, i, sv[a]);
   }
 }
 
@@ -1997,7 +2073,9 @@ template <class P>
 __global__ void __launch_bounds__(256) k_init_f(Dev d, const double *src, int a) {
   const Blk bk{(int)blockIdx.x, (int)gridDim.x};
   using R = typename P::R;
-  FSLBM_GRID_STRIDE(i) st<P>(d.f_src, a, d.N, i, (R)(P::EXACT ? src[i] : src[i] - wgt(a)));
+  // (an exact conversion for values exported from the same precision)
+  FSLBM_GRID_STRIDE(i)
+      st<P>(d.f_src, a, d.N, i, (typename P::S)(R)(P::EXACT ? src[i] : src[i] - wgt(a)));
 }
 
 // Export one quantity as FP64: what = 0 phi, 1 mass (rho on liquid cells),
