@@ -1000,17 +1000,29 @@ struct K_conv_types {
     const int k = base + threadIdx.x;
     bool F = false, E = false;
     int x = 0, y = 0, z = 0;
+    // the cell's flag and both flags of its neighbours in one batch.  A
+    // neighbour's candidate bits do not change here; the flag of t+1 of a
+    // gas or liquid neighbour changes only by the same "becomes interface"
+    // write from every candidate next to it, so the value read here serves
+    // that write.
+    uint8_t fdn[Q], fsn[Q];
     if (k < n) {
       const long long i = d.clist[k];
       coords(d, i, x, y, z);
       const uint8_t fd = d.flag_dst[i];
+#pragma unroll
+      for (int a = 1; a < Q; ++a) {
+        const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
+        fdn[a] = d.flag_dst[j];
+        fsn[a] = d.flag_src[j];
+      }
       if (fd & CAND_F) {
         F = true;
       } else if (fd & CAND_E) {
         E = true;
 #pragma unroll
         for (int a = 1; a < Q; ++a)
-          if (d.flag_dst[nbr(d, x, y, z, CX[a], CY[a], CZ[a])] & CAND_F) E = false;
+          if (fdn[a] & CAND_F) E = false;
       }
       if (F) d.flag_dst[i] = (uint8_t)((fd & ~TYPE_MASK) | T_LIQ);
       if (E) d.flag_dst[i] = (uint8_t)((fd & ~TYPE_MASK) | T_GAS);
@@ -1022,10 +1034,10 @@ struct K_conv_types {
     if (F || E) {
 #pragma unroll
       for (int a = 1; a < Q; ++a) {
-        const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
-        const uint8_t tj = d.flag_src[j] & TYPE_MASK;
+        const uint8_t tj = fsn[a] & TYPE_MASK;
         if ((F && tj == T_GAS) || (E && tj == T_LIQ)) {
-          d.flag_dst[j] = (uint8_t)((d.flag_dst[j] & ~TYPE_MASK) | T_IFACE);
+          const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
+          d.flag_dst[j] = (uint8_t)((fdn[a] & ~TYPE_MASK) | T_IFACE);
           if (claim_cell(d, j)) won |= 1u << a;
         }
       }
@@ -1307,9 +1319,12 @@ struct K_gather {
     long long v[VACC] = {0, 0, 0, 0, 0, 1};
     if (k < n) {
       const long long i = d.ilist_dst[k];
+      // what every listed cell needs, in one batch with its flags
       const uint8_t fd = d.flag_dst[i];
-      R ph;
-      if ((fd & GATHER) || (d.flag_src[i] & TYPE_MASK) != T_IFACE) {
+      const uint8_t fsrc = d.flag_src[i];
+      const int slot = d.bslot[i];
+      R ph = ((const R *)d.phi_dst)[i];
+      if ((fd & GATHER) || (fsrc & TYPE_MASK) != T_IFACE) {
         // a receiver of excess or a new interface cell
         R add = (R)0;
         bool touched = false;
@@ -1340,11 +1355,10 @@ struct K_gather {
         }
         ph = m / ((const R *)d.rhoI)[i];
         ((R *)d.phi_dst)[i] = ph;
-      } else {
-        // untouched interface cell: phi = m / rho as written by k_iface
-        ph = ((const R *)d.phi_dst)[i];
       }
-      key = d.bslot[i];
+      // (an untouched interface cell keeps phi = m / rho as written by
+      // k_iface)
+      key = slot;
       const ExTerm t = ex_split(1.0 - (double)ph);
 #pragma unroll
       for (int c = 0; c < EX_WORDS; ++c) v[c] = t.w[c];
