@@ -1188,19 +1188,18 @@ __device__ __forceinline__ uint32_t adj_mask(int p) { return ADJ27[p]; }
 // (a) x's gas-region neighbours (new state) are connected inside x's 3x3x3
 // block, and (b) every filled neighbour y of x shares a gas-region
 // neighbour with x.  Returns true when a relabelling is needed.
-__device__ bool split_possible(const Dev &d, int x, int y, int z) {
+// n1, n0: the flags of t+1 and t over the block (index blk_pos).
+__device__ __forceinline__ bool split_possible(const uint8_t (&n1)[27], const uint8_t (&n0)[27]) {
   uint32_t setm = 0, filled = 0;
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        if (dx == 0 && dy == 0 && dz == 0) continue;
-        const long long j = nbr(d, x, y, z, dx, dy, dz);
-        const uint8_t tn = d.flag_dst[j] & TYPE_MASK;
-        const int p = blk_pos(dx, dy, dz);
-        if (in_gas_region(tn)) setm |= 1u << p;
-        const int l1 = (dx != 0) + (dy != 0) + (dz != 0);
-        if (l1 <= 2 && (d.flag_src[j] & TYPE_MASK) == T_IFACE && tn == T_LIQ) filled |= 1u << p;
-      }
+#pragma unroll
+  for (int p = 0; p < 27; ++p) {
+    if (p == 13) continue;
+    const uint8_t tn = n1[p] & TYPE_MASK;
+    if (in_gas_region(tn)) setm |= 1u << p;
+    const int dx = p % 3 - 1, dy = (p / 3) % 3 - 1, dz = p / 9 - 1;
+    const int l1 = (dx != 0) + (dy != 0) + (dz != 0);
+    if (l1 <= 2 && (n0[p] & TYPE_MASK) == T_IFACE && tn == T_LIQ) filled |= 1u << p;
+  }
   const uint32_t n18 = adj_mask(13);
   const uint32_t targets = setm & n18;
   if (!targets) return true;
@@ -1241,9 +1240,22 @@ struct K_excess {
     const int slot = d.bslot[i];
     R *mass = (R *)d.mass;
     const R m_i = mass[i], rho_i = ((const R *)d.rhoI)[i];
+    // the flags of t+1 and t over the 3x3x3 block (the split test needs
+    // the corners too), also in that batch
+    uint8_t n1[27], n0[27];
+#pragma unroll
+    for (int p = 0; p < 27; ++p) {
+      if (p == 13) {
+        n1[p] = n0[p] = 0;
+        continue;
+      }
+      const long long j = nbr(d, x, y, z, p % 3 - 1, (p / 3) % 3 - 1, p / 9 - 1);
+      n1[p] = d.flag_dst[j];
+      n0[p] = d.flag_src[j];
+    }
     uint8_t fn[Q];
 #pragma unroll
-    for (int a = 1; a < Q; ++a) fn[a] = d.flag_dst[nbr(d, x, y, z, CX[a], CY[a], CZ[a])];
+    for (int a = 1; a < Q; ++a) fn[a] = n1[blk_pos(CX[a], CY[a], CZ[a])];
     if (t == T_IFACE && (tn == T_LIQ || tn == T_GAS)) {
       const bool filled = tn == T_LIQ;
       const R e = filled ? m_i - rho_i : m_i;
@@ -1267,7 +1279,7 @@ struct K_excess {
         mass[i] = rho_i;
         ((R *)d.phi_src)[i] = (R)1;
         ((R *)d.phi_dst)[i] = (R)1;
-        if (split_possible(d, x, y, z)) {
+        if (split_possible(n1, n0)) {
           trig = true;
           atomicOr(&d.b_affect[slot], 1);
         }
