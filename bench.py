@@ -354,7 +354,7 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16dev"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--phase-period", type=int, default=10,
+    ap.add_argument("--phase-period", type=int, default=25,
                     help="bracket every N-th timed step with per-phase HIP events (the "
                          "kernel time of the roofline figure); each event delays the next "
                          "kernel by a few microseconds, so sampling keeps the window close "
