@@ -55,7 +55,7 @@ def lib():
         L = C.CDLL(LIB)
         P = C.c_void_p
         L.orc_create.restype = P
-        L.orc_create.argtypes = [C.POINTER(_Params), P, P, P, P, P, P, P, P, P, C.c_int32, P,
+        L.orc_create.argtypes = [C.POINTER(_Params), P, P, P, P, P, P, P, P, P, C.c_int32, P, P,
                                  C.c_int64, C.c_int32, C.c_double, C.c_char_p, C.c_int32]
         L.orc_destroy.argtypes = [P]
         L.orc_step.argtypes = [P, C.c_int32]
@@ -148,7 +148,7 @@ class Oracle:
     explicit arrays."""
 
     def __init__(self, params: dict, cell_type, phi, rho, u, bubble_id, bubbles,
-                 f_init=None, step0=0, next_id0=0, bucket0=0.0):
+                 f_init=None, step0=0, next_id0=0, bucket0=0.0, mass_init=None):
         self.params = dict(params)
         self.nx, self.ny, self.nz = params["nx"], params["ny"], params["nz"]
         self.N = self.nx * self.ny * self.nz
@@ -163,10 +163,12 @@ class Oracle:
         b_vs = np.asarray([b[2] for b in bubbles], np.float64)
         b_pi = np.asarray([b[3] for b in bubbles], np.float64)
         fi = None if f_init is None else np.ascontiguousarray(f_init, np.float64)
+        mi = None if mass_init is None else np.ascontiguousarray(mass_init, np.float64)
         err = C.create_string_buffer(256)
         h = lib().orc_create(C.byref(p), _ptr(t), _ptr(ph), _ptr(r), _ptr(uu), _ptr(bid),
                              _ptr(b_id), _ptr(b_fl), _ptr(b_vs), _ptr(b_pi), len(bubbles),
-                             _ptr(fi), int(step0), int(next_id0), float(bucket0), err, 256)
+                             _ptr(fi), _ptr(mi), int(step0), int(next_id0), float(bucket0),
+                             err, 256)
         if not h:
             raise ValueError("oracle rejected input: " + err.value.decode())
         self._h = C.c_void_p(h)

@@ -473,7 +473,8 @@ static void compute_mass(orc *o) {
 orc *orc_create(const orc_params *p, const uint8_t *type, const double *phi, const double *rho,
                 const double *u, const int32_t *id, const int32_t *b_id, const int32_t *b_flags,
                 const double *b_vstar, const double *b_pinit, int32_t nb, const double *f_init,
-                int64_t step0, int32_t next_id0, double bucket0, char *err, int32_t errlen) {
+                const double *mass_init, int64_t step0, int32_t next_id0, double bucket0,
+                char *err, int32_t errlen) {
   if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0 || p->tau <= 0.5) {
     set_err(err, errlen, "bad sizes or tau");
     return NULL;
@@ -601,7 +602,8 @@ orc *orc_create(const orc_params *p, const uint8_t *type, const double *phi, con
       for (int a = 0; a < Q; ++a) o->f[a * N + i] = 0.0;
     }
     if (t == ORC_I) {
-      o->m[i] = o->phi[i] * o->rho[i]; /* m = phi rho (Sec. 2.2) */
+      /* m = phi rho (Sec. 2.2), or the mass of a saved state */
+      o->m[i] = mass_init ? mass_init[i] : o->phi[i] * o->rho[i];
       o->n_iface += 1;
     } else if (t == ORC_L) {
       o->m[i] = o->rho[i];

@@ -39,12 +39,15 @@ typedef struct orc orc;
 /* Build the oracle state.  Arrays are flat, i = x + nx*(y + ny*z); u is SoA
  * [3][N].  bubbles: b_vstar[k] > 0 is used as the initial volume V*, else
  * V* = V(0) * b_pinit[k] / p0.  f_init may be NULL (then f = f_eq(rho, u)).
+ * mass_init may be NULL (then an interface cell starts with m = phi rho,
+ * Sec. 2.2); otherwise it gives the interface masses of a saved state, so
+ * that a run continues from that state exactly.
  * Returns NULL and writes a message into err on invalid input. */
 orc *orc_create(const orc_params *p, const uint8_t *type, const double *phi,
                 const double *rho, const double *u, const int32_t *id,
                 const int32_t *b_id, const int32_t *b_flags, const double *b_vstar,
                 const double *b_pinit, int32_t nb, const double *f_init,
-                int64_t step0, int32_t next_id0, double bucket0,
+                const double *mass_init, int64_t step0, int32_t next_id0, double bucket0,
                 char *err, int32_t errlen);
 void orc_destroy(orc *o);
 void orc_set_threads(int32_t n);

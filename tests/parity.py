@@ -80,6 +80,21 @@ def compare_state(o, g, label: str, tol: float = TOL64, fields=True, exact=True)
     return out
 
 
+def oracle_from_state(params: dict, state: dict, bubbles: dict, scalars: dict):
+    """An oracle that continues from a saved state: the fields of a read
+    (of the oracle or of a GPU domain), its bubble table and its step,
+    next ID and bucket."""
+    import oracle
+
+    b = [(int(i), int(fl), float(vs), float(p))
+         for i, fl, vs, p in zip(bubbles["id"], bubbles["flags"], bubbles["v_star"],
+                                 bubbles["pressure"])]
+    return oracle.Oracle(params, state["cell_type"], state["phi"], state["rho"], state["u"],
+                         state["bubble_id"], b, f_init=state["f"], mass_init=state["mass"],
+                         step0=scalars["step"], next_id0=scalars["next_id"],
+                         bucket0=scalars["bucket"])
+
+
 def run_pair(sc, steps: int, every: int, name: str, precision="fp64", **over):
     import oracle
     from paper_1604_01632_amd import Domain
