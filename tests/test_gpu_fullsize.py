@@ -1,0 +1,292 @@
+"""The GPU library at full size: the 256^3 thread lattice that the benchmark
+times, in the benchmark's own launch configuration (one domain, FP32, the
+phase timing of the timed window on).  The oracle cannot run the scene's
+horizon at this size, but it can run whole steps: it takes over a state
+read from the GPU and runs the same step, element by element.  Over the
+horizon, the FP32 form is held to the accuracy bounds of the reduced
+precision forms against the FP64 form, which itself reproduces the oracle
+bit for bit (here on the first step, at full size)."""
+import gc
+import os
+
+import numpy as np
+import pytest
+
+import scenes
+from scenes import GAS, IFACE, INLET, LIQ
+from tests.parity import compare_state, oracle_from_state, say
+
+pytestmark = pytest.mark.gpu
+
+WARMUP = 1000        # untimed steps of the benchmark before its window
+PHASE_PERIOD = 25    # the benchmark's phase-timing period in the window
+HORIZON = 4000
+
+# One FP32 step from an FP32-representable state against the FP64 oracle.
+# Every stored value is the result of a few dozen FP32 operations (unit
+# roundoff 2^-24 = 6e-8) on terms of the size of the equilibrium
+# populations, w_a rho: a PDF therefore carries an absolute error of a few
+# ulp of w_a, whatever its own size (a reconstructed population can come
+# out far below w_a), and agrees to 1e-5 relative to max(|f|, w_a).  Fill
+# levels and masses (order one) agree to 1e-5 absolute.  Bubble volumes are exact sums of the fill levels (order 1e3
+# cells per bubble): 1e-6 relative; V* and p follow them.  The total mass is
+# the FP64 sum of FP32 cell values: 1e-7 relative.
+TOL_F = 1e-5
+W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+# Two discrete choices of an interface cell are taken on its normal n, in
+# the precision of the form: which directions are reconstructed (c_a.n > 0)
+# and the dominant axis of the height function.  Each component of n is a
+# sum of 18 terms of size at most 4 |phi| (phi <= 1.1), so in FP32 it is off
+# by at most about 18 * 2^-24 * 4.4 * 18 = 8.5e-5 in the worst case, and
+# c_a.n or the gap between two |n_k| by twice that: within that band of a
+# tie the FP32 form may choose the other way.  Only such a cell may hold
+# PDFs beyond TOL_F (its other values are bounded as usual).
+TIE_BAND = 2e-4
+TOL_FIELD = 1e-5
+TOL_BUBBLE = 1e-6
+TOL_MASS32 = 1e-7
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1604_01632_amd as pkg
+    pkg.lib()  # fails loudly if the library is missing
+    yield
+
+
+@pytest.fixture(scope="module")
+def p1():
+    return scenes.config("p1")
+
+
+def _oracle():
+    import oracle
+    oracle.build(force=False)
+    oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    return oracle
+
+
+def _free(*objs):
+    import torch
+    for o in objs:
+        if hasattr(o, "close"):
+            o.close()
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def _bench_domain(sc):
+    """A domain as the benchmark builds it, with the window's phase timing
+    switched on once the warm-up is done (see `_advance`)."""
+    from paper_1604_01632_amd import Domain
+    return Domain.from_scene(sc, "fp32")
+
+
+def _advance(d, to_step: int) -> None:
+    """Step a benchmark domain to `to_step`: untimed up to the end of the
+    warm-up, with the window's phase timing from there on."""
+    import paper_1604_01632_amd as F
+    s = d.read(())["scalars"]["step"]
+    if s < WARMUP:
+        n = min(WARMUP, to_step) - s
+        d.step(n)
+        s += n
+    if s >= WARMUP:
+        F.fslbm_set_timing(d.handle, PHASE_PERIOD)
+        if to_step > s:
+            d.step(to_step - s)
+    d.sync()
+
+
+@pytest.mark.timeout(900)
+def test_p1_first_step_fp64_matches_oracle_bitwise(p1):
+    """First step of the 256^3 scene in the FP64 form, bit for bit against
+    the oracle: every rule at full size, and the labelling of the whole gas
+    region (every first step labels it all)."""
+    from paper_1604_01632_amd import Domain
+    oracle = _oracle()
+    say(f"[fullsize] p1 fp64 step 1: {p1.nx}x{p1.ny}x{p1.nz}")
+    g = Domain.from_scene(p1, "fp64")
+    o = oracle.Oracle.from_scene(p1)
+    o.step(1)
+    g.step(1)
+    compare_state(o, g, "p1 fp64 step 1", exact=True)
+    n = len(o.bubbles()["id"])
+    say(f"[fullsize] p1 fp64 step 1: bitwise equal, {n} bubbles")
+    assert n == 16
+    _free(g, o)
+
+
+def _near_tie(i, t_before, normal, c, shape):
+    """Smallest distance of an FP64 decision of interface cell i from its
+    tie: |c_a.n| over the directions whose source cell is interface or
+    liquid, and the gap between the two largest |n_k|."""
+    nz, ny, nx = shape
+    n = normal[:, i]
+    x, y, z = i % nx, (i // nx) % ny, i // (nx * ny)
+    d = np.inf
+    for a in range(1, 19):
+        sx, sy, sz = (x - c[a, 0]) % nx, (y - c[a, 1]) % ny, (z - c[a, 2]) % nz
+        if t_before[sx + nx * (sy + ny * sz)] in (IFACE, LIQ):
+            d = min(d, abs(float(c[a] @ n)))
+    an = np.sort(np.abs(n))
+    return min(d, float(an[2] - an[1]))
+
+
+def _compare_fp32_step(do, bo, so, dg, bg, sg, N, eps, audit):
+    to, tg = do["cell_type"], dg["cell_type"]
+    bad = np.nonzero(to != tg)[0]
+    if bad.size:
+        ph = do["phi"][bad]
+        margin = np.minimum(np.abs(ph - (1 + eps)), np.abs(ph + eps))
+        raise AssertionError(f"{bad.size} cell types differ, e.g. {bad[:5].tolist()}; "
+                             f"min threshold margin {margin.min():.3e}")
+    assert np.array_equal(do["bubble_id"], dg["bubble_id"]), "bubble IDs differ"
+    fl = (to == IFACE) | (to == LIQ)
+    cells = np.nonzero(fl)[0]
+    fo, fg = do["f"].reshape(19, N), dg["f"].reshape(19, N)
+    rel_f, worst, beyond = 0.0, None, np.zeros(cells.size, bool)
+    for a in range(19):
+        x, y = fo[a, fl], fg[a, fl]
+        assert np.all(x > 0)
+        e = np.abs(y - x) / np.maximum(x, W[a])
+        beyond |= e > TOL_F
+        e[beyond] = 0.0  # judged by the audit below
+        k = int(np.argmax(e))
+        if e[k] > rel_f:
+            rel_f, worst = float(e[k]), (a, int(cells[k]), float(x[k]), float(y[k]))
+    if worst is not None:
+        a, i, x, y = worst
+        say(f"[fullsize] worst PDF within the bound: direction {a}, cell {i}, oracle {x:.9e}, "
+            f"gpu {y:.9e}")
+    odd = cells[beyond]
+    ties = [audit(int(i)) for i in odd]
+    say(f"[fullsize] {odd.size} cell(s) with PDFs beyond {TOL_F:g}: types at t "
+        f"{sorted(set(int(audit.t_before[i]) for i in odd))}, distance of an FP64 choice "
+        f"from its tie at most {max(ties, default=0.0):.2e}")
+    assert all(audit.t_before[i] == IFACE for i in odd)
+    assert max(ties, default=0.0) <= TIE_BAND, "PDFs differ at a cell with no near-tie choice"
+    assert odd.size <= max(1, cells.size // 100000)
+    it = to == IFACE
+    err = {k: float(np.max(np.abs(do[k][it] - dg[k][it]))) for k in ("phi", "mass")}
+    assert bo["id"].tolist() == bg["id"].tolist(), "bubble IDs of the table differ"
+    assert bo["n_cells"].tolist() == bg["n_cells"].tolist(), "bubble cell counts differ"
+    assert bo["flags"].tolist() == bg["flags"].tolist()
+    berr = {k: float(np.max(np.abs(bo[k] - bg[k]) / np.abs(bo[k]))) for k in
+            ("volume", "v_star", "pressure")}
+    merr = abs(so["total_mass"] - sg["total_mass"]) / abs(so["total_mass"])
+    say(f"[fullsize] fp32 step vs oracle: f {rel_f:.2e}, phi {err['phi']:.2e}, mass "
+        f"{err['mass']:.2e}, bubbles {', '.join(f'{k} {v:.2e}' for k, v in berr.items())}, "
+        f"total mass {merr:.2e}")
+    assert rel_f <= TOL_F
+    assert err["phi"] <= TOL_FIELD and err["mass"] <= TOL_FIELD
+    for v in berr.values():
+        assert v <= TOL_BUBBLE
+    assert merr <= TOL_MASS32
+    assert so["step"] == sg["step"] and so["next_id"] == sg["next_id"]
+
+
+@pytest.mark.timeout(900)
+def test_p1_topology_step_fp32_in_benchmark_window(p1):
+    """A step with a topology change inside the benchmark's timed window
+    (FP32, 256^3, benchmark launch configuration): the oracle takes over
+    the state the GPU held before that step and runs it; cell types, bubble
+    IDs and the bubble table agree exactly, the fields within FP32 rounding.
+    The GPU path is deterministic, so the run that finds the step and the
+    run that is compared reach the same state."""
+    oracle = _oracle()
+    g = _bench_domain(p1)
+    _advance(g, WARMUP)
+    t0 = g.read(())["scalars"]["n_topology"]
+    t_star = None
+    for k in range(WARMUP + 1, WARMUP + 600):
+        g.step(1)
+        if g.read(())["scalars"]["n_topology"] > t0:
+            t_star = k
+            break
+    _free(g)
+    assert t_star is not None, "no topology change within 600 steps of the window start"
+    say(f"[fullsize] p1 fp32: first topology change of the window at step {t_star}")
+
+    g = _bench_domain(p1)
+    _advance(g, t_star - 1)
+    before = g.read()
+    bb, sb = g.bubbles(), before["scalars"]
+    assert sb["step"] == t_star - 1
+    o = oracle_from_state(p1.params(), before, bb, sb)
+    t_before = before["cell_type"].copy()
+    del before
+    gc.collect()
+    _, normal = o.geometry()
+    c = oracle.lattice()[0]
+
+    def audit(i):
+        return _near_tie(i, t_before, normal, c, (p1.nz, p1.ny, p1.nx))
+    audit.t_before = t_before
+    o.step(1)
+    g.step(1)
+    dg = g.read()
+    bg, sg = g.bubbles(), dg["scalars"]
+    assert sg["n_topology"] == sb["n_topology"] + 1
+    do, bo, so = o.read(), o.bubbles(), o.scalars()
+    assert so["n_topology"] == 1, "the oracle saw no topology change in this step"
+    say(f"[fullsize] p1 fp32 step {t_star}: bubbles {len(bb['id'])} -> {len(bg['id'])}, "
+        f"next ID {sb['next_id']} -> {sg['next_id']}")
+    _compare_fp32_step(do, bo, so, dg, bg, sg, p1.n, p1.params().get("eps_convert", 1e-2),
+                       audit)
+    _free(g, o)
+
+
+def _closed_layer_and_ids(t, bid, live, shape):
+    nz, ny, nx = shape
+    t3 = t.reshape(nz, ny, nx)
+    liq = t3 == LIQ
+    gas = (t3 == GAS) | (t3 == INLET)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if not 1 <= abs(dx) + abs(dy) + abs(dz) <= 2:
+                    continue
+                sh = np.roll(gas, (-dz, -dy, -dx), (0, 1, 2))
+                assert not np.any(liq & sh), "liquid cell next to a gas cell"
+    inset = np.isin(t, [GAS, IFACE, INLET])
+    assert set(np.unique(bid[inset]).tolist()) == set(live)
+    assert np.all(bid[~inset] == -1)
+
+
+@pytest.mark.timeout(900)
+def test_p1_fp32_against_fp64_over_horizon(p1):
+    """The 256^3 scene over its 4000-step horizon (the benchmark's window
+    included) in FP32 and in FP64: the same bubble count, volumes within
+    1e-3 relative, total-mass drift at most 1e-6 relative, and in FP32 a
+    closed interface layer and a live bubble ID on every gas-region cell."""
+    from paper_1604_01632_amd import Domain
+    out = {}
+    for prec in ("fp64", "fp32"):
+        d = Domain.from_scene(p1, prec) if prec == "fp64" else _bench_domain(p1)
+        m0 = d.read(())["scalars"]["total_mass"]
+        for k in range(1, HORIZON // 1000 + 1):
+            if prec == "fp32":
+                _advance(d, 1000 * k)
+            else:
+                d.step(1000)
+                d.sync()
+        r = d.read(("cell_type", "bubble_id"))
+        s = r["scalars"]
+        b = d.bubbles()
+        out[prec] = (b, abs(s["total_mass"] - m0) / m0, s["n_topology"])
+        say(f"[fullsize] p1 {prec} step {s['step']}: {len(b['id'])} bubbles, "
+            f"{s['n_topology']} topology changes, mass drift {out[prec][1]:.2e}")
+        assert s["step"] == HORIZON
+        if prec == "fp32":
+            _closed_layer_and_ids(r["cell_type"], r["bubble_id"], b["id"].tolist(),
+                                  (p1.nz, p1.ny, p1.nx))
+        _free(d)
+    ref, b = out["fp64"][0], out["fp32"][0]
+    assert out["fp64"][2] > 0  # the threads broke up
+    assert len(b["id"]) == len(ref["id"]) > 16
+    assert np.allclose(np.sort(b["volume"]), np.sort(ref["volume"]), rtol=1e-3)
+    assert out["fp32"][1] <= 1e-6
