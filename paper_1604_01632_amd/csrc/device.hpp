@@ -38,9 +38,23 @@ constexpr int SUB_MASS = 256;
 constexpr int FX_VOL = 50;
 constexpr int FX_SPLIT = 25;
 
-// Per-bubble accumulator: exact-sum words of the gas volume, then the
-// interface-cell count.
-constexpr int VACC = EX_WORDS + 1;
+// Per-bubble accumulator of the interface cells' gas volumes 1 - phi and
+// their count.  A term computed in double from phi in (-1, 3) is an integer
+// multiple of 2^-53 below 2 in magnitude (1 - phi lies in [1, 2) for
+// phi <= 0 and in (0.5, 1] for 0 < phi < 0.5, where the spacing is 2^-52 or
+// 2^-53; for 0.5 <= phi < 3 the difference is exact, a multiple of the
+// spacing of phi), so q = (1 - phi) 2^53 is an integer with |q| < 2^54.  It
+// is added as three chunks of 18 bits (q = c0 + c1 2^18 + c2 2^36, c2
+// signed), whose sums over a wave fit in 32 bits.  Any other term goes into
+// the exact-sum words.  Layout: VA_EX exact-sum words, VA_FIX chunk sums,
+// the count.
+constexpr int VA_EX = 0;
+constexpr int VA_FIX = EX_WORDS;
+constexpr int VA_FIXN = 3;
+constexpr int VA_FIX_BITS = 18;
+constexpr int VA_FIX_SCALE = 53;
+constexpr int VA_CNT = EX_WORDS + VA_FIXN;
+constexpr int VACC = EX_WORDS + VA_FIXN + 1;
 // Per-new-component accumulators of a labelling event: exact-sum words of
 // the volume and of V*, then ncells, ngas, niface, inlet cells.
 constexpr int NACC = 2 * EX_WORDS + 4;
@@ -145,12 +159,44 @@ __device__ __forceinline__ long long wave_sum(long long v) {
   return v;
 }
 
-// Adds the NV values of every active lane (key >= 0) into
-// base[(key * stride + sub) * NV + k], one atomic per distinct key per wave.
-// Every lane of the wave must call it.
-template <int NV>
-__device__ __forceinline__ void wave_add_by_key(int key, const long long *v,
-                                                unsigned long long *base, int stride, int sub) {
+__device__ __forceinline__ int wave_sum32(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Block-level combining of keyed sums: a small LDS table with one entry per
+// key the block has seen (claimed by compare-and-swap).  Waves add their
+// per-key sums into it, and the block adds every entry to global memory
+// once (key_sums_flush), so that blocks, not waves, contend for the global
+// words.  Keys beyond the table's KB entries go to global memory at once.
+// The sums are integers: the result does not depend on the order.
+template <int NV, int KB>
+struct KeySums {
+  int key[KB];
+  unsigned long long acc[KB][NV];
+};
+
+// Every thread of the block must call it (it synchronises the block).
+template <int NV, int KB>
+__device__ __forceinline__ void key_sums_init(KeySums<NV, KB> &t) {
+  for (int e = threadIdx.x; e < KB; e += blockDim.x) {
+    t.key[e] = -1;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) t.acc[e][k] = 0;
+  }
+  __syncthreads();
+}
+
+// Adds the NV values of every active lane (key >= 0), summed per distinct
+// key over the wave (in 64 or, for T = int, 32 bits: the caller bounds the
+// sums), into the block's table; the words of a key outside the table go to
+// base[(key * stride + sub) * row + off + k] at once.  Every lane of the
+// wave must call it.
+template <int NV, int KB, class T>
+__device__ __forceinline__ void wave_add_by_key_lds(int key, const T *v, KeySums<NV, KB> &t,
+                                                    unsigned long long *base, int stride,
+                                                    int sub, int row, int off) {
   bool active = key >= 0;
   unsigned long long m = __ballot(active);
   const int lane = __lane_id();
@@ -158,15 +204,46 @@ __device__ __forceinline__ void wave_add_by_key(int key, const long long *v,
     int leader = __ffsll((long long)m) - 1;
     int lkey = __shfl(key, leader, 64);
     bool mine = active && key == lkey;
+    long long s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      long long s = wave_sum(mine ? v[k] : 0ll);
-      if (lane == leader)
-        atomicAdd(&base[((long long)lkey * stride + sub) * NV + k], (unsigned long long)s);
+      if constexpr (sizeof(T) == 4) s[k] = wave_sum32(mine ? v[k] : 0);
+      else s[k] = wave_sum(mine ? (long long)v[k] : 0ll);
+    }
+    if (lane == leader) {
+      int e = 0;
+      for (; e < KB; ++e) {
+        const int prev = atomicCAS(&t.key[e], -1, lkey);
+        if (prev == -1 || prev == lkey) break;
+      }
+      if (e < KB) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) atomicAdd(&t.acc[e][k], (unsigned long long)s[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+          atomicAdd(&base[((long long)lkey * stride + sub) * row + off + k],
+                    (unsigned long long)s[k]);
+      }
     }
     unsigned long long mm = __ballot(mine);
     if (mine) active = false;
     m &= ~mm;
+  }
+}
+
+// Adds the table to base[(key * stride + sub) * row + off + k].  Every
+// thread of the block must call it, after its last wave_add_by_key_lds.
+template <int NV, int KB>
+__device__ __forceinline__ void key_sums_flush(KeySums<NV, KB> &t, unsigned long long *base,
+                                               int stride, int sub, int row, int off) {
+  __syncthreads();
+  for (int q = threadIdx.x; q < KB * NV; q += blockDim.x) {
+    const int e = q / NV, k = q % NV;
+    const int key = t.key[e];
+    const unsigned long long x = t.acc[e][k];
+    if (key >= 0 && x != 0)
+      atomicAdd(&base[((long long)key * stride + sub) * row + off + k], x);
   }
 }
 

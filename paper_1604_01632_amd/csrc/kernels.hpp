@@ -1322,13 +1322,15 @@ struct K_gather {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   using R = typename P::R;
+  __shared__ KeySums<VA_FIXN + 1, 16> vol;
+  key_sums_init(vol);
   const int sub = bk.id % SUB;
   const int n = d.sc->n_il_dst;  // interface list of t+1, rebuilt before this kernel
   const int nch = (n + THREADS - 1) / THREADS, m = nch < bk.n ? nch : bk.n;
   for (int c = bk.id; c < nch; c += bk.n) {
     const int k = xcd_chunk(c, m) * THREADS + (int)threadIdx.x;
     int key = -1;
-    long long v[VACC] = {0, 0, 0, 0, 0, 1};
+    int v[VA_FIXN + 1] = {0, 0, 0, 1};  // chunks of (1 - phi) 2^53, count
     if (k < n) {
       const long long i = d.ilist_dst[k];
       // what every listed cell needs, in one batch with its flags
@@ -1371,12 +1373,26 @@ struct K_gather {
       // (an untouched interface cell keeps phi = m / rho as written by
       // k_iface)
       key = slot;
-      const ExTerm t = ex_split(1.0 - (double)ph);
-#pragma unroll
-      for (int c = 0; c < EX_WORDS; ++c) v[c] = t.w[c];
+      const double gv = 1.0 - (double)ph;
+      if (fabs(gv) < 2.0) {
+        // an integer below 2^54 in magnitude, taken exactly
+        const long long q = (long long)(gv * 0x1p53);
+        const long long lo = (1ll << VA_FIX_BITS) - 1;
+        v[0] = (int)(q & lo);
+        v[1] = (int)((q >> VA_FIX_BITS) & lo);
+        v[2] = (int)(q >> (2 * VA_FIX_BITS));
+      } else {
+        // outside the chunk range (a saved state may hold any fill
+        // level): straight into the exact-sum words
+        const ExTerm t = ex_split(gv);
+        unsigned long long *w = d.b_vacc + ((long long)slot * SUB + sub) * VACC + VA_EX;
+        for (int c = 0; c < EX_WORDS; ++c)
+          if (t.w[c]) atomicAdd(&w[c], (unsigned long long)t.w[c]);
+      }
     }
-    wave_add_by_key<VACC>(key, v, d.b_vacc, SUB, sub);
+    wave_add_by_key_lds(key, v, vol, d.b_vacc, SUB, sub, VACC, VA_FIX);
   }
+  key_sums_flush(vol, d.b_vacc, SUB, sub, VACC, VA_FIX);
 }
 };
 
@@ -1484,31 +1500,53 @@ struct K_list_fill {
 // ------------------------------------------------------- bubble volumes
 
 // Per-bubble volume V = (gas + inlet cells) + sum over interface cells of
-// (1 - phi), exactly rounded (one thread per bubble slot over the whole
+// (1 - phi), exactly rounded (SUB lanes per bubble slot over the whole
 // grid); orphan bucket and total mass (block 0).  Runs at the start of the
 // first labelling kernel, every step.
 __device__ __forceinline__ void bubble_volumes(const Dev &d, Blk bk) {
   __shared__ long long red[4][2];
-  const long long g0 = (long long)bk.id * blockDim.x + threadIdx.x;
-  for (long long s = g0; s < d.max_bubbles; s += (long long)bk.n * blockDim.x) {
-    if (!d.b_live[s]) continue;
-    unsigned long long *acc = d.b_vacc + s * SUB * VACC;
-    long long w[EX_WORDS] = {0, 0, 0, 0, 0};
-    long long cnt = 0;
-    // all words first (independent loads), then clear them
+  // one lane per (slot, sub-slot): the SUB lanes of a slot are
+  // consecutive lanes of one wave (SUB divides 64, blocks are whole
+  // waves), load and clear their words at once and sum them with shuffles
+  static_assert(64 % SUB == 0, "the sub-slots of a slot share a wave");
+  const long long nq = (long long)d.max_bubbles * SUB;
+  for (long long q0 = (long long)bk.id * blockDim.x; q0 < nq;
+       q0 += (long long)bk.n * blockDim.x) {  // uniform per block
+    const long long q = q0 + threadIdx.x;
+    const long long s = q / SUB;
+    const bool live = q < nq && d.b_live[s];
+    long long w[VACC];
 #pragma unroll
-    for (int k = 0; k < SUB; ++k) {
+    for (int c = 0; c < VACC; ++c) w[c] = 0;
+    if (live) {
+      unsigned long long *acc = d.b_vacc + q * VACC;  // slot s, sub-slot q % SUB
 #pragma unroll
-      for (int c = 0; c < EX_WORDS; ++c) w[c] += ll(acc[VACC * k + c]);
-      cnt += ll(acc[VACC * k + EX_WORDS]);
+      for (int c = 0; c < VACC; ++c) w[c] = ll(acc[c]);
+#pragma unroll
+      for (int c = 0; c < VACC; ++c) acc[c] = 0;
     }
 #pragma unroll
-    for (int k = 0; k < SUB * VACC; ++k) acc[k] = 0;
-    const ExTerm g = ex_split((double)d.b_ngas[s]);
+    for (int m = SUB / 2; m >= 1; m >>= 1)
 #pragma unroll
-    for (int c = 0; c < EX_WORDS; ++c) w[c] += g.w[c];
-    d.b_vol[s] = ex_value(w);
-    d.b_niface[s] = cnt;
+      for (int c = 0; c < VACC; ++c) w[c] += __shfl_xor(w[c], m, 64);
+    if (live && q % SUB == 0) {
+      long long e[EX_WORDS];
+#pragma unroll
+      for (int c = 0; c < EX_WORDS; ++c) e[c] = w[VA_EX + c];
+      // the chunk sums (below 2^42 in magnitude: exact doubles) and the
+      // gas cells join the exact sum
+#pragma unroll
+      for (int c = 0; c < VA_FIXN; ++c) {
+        const ExTerm t = ex_split(ldexp((double)w[VA_FIX + c], VA_FIX_BITS * c - VA_FIX_SCALE));
+#pragma unroll
+        for (int k = 0; k < EX_WORDS; ++k) e[k] += t.w[k];
+      }
+      const ExTerm g = ex_split((double)d.b_ngas[s]);
+#pragma unroll
+      for (int c = 0; c < EX_WORDS; ++c) e[c] += g.w[c];
+      d.b_vol[s] = ex_value(e);
+      d.b_niface[s] = w[VA_CNT];
+    }
   }
   if (bk.id != 0) return;  // uniform per block
   // total mass diagnostic: block reduction of the replicated slots
@@ -1911,6 +1949,8 @@ struct K_label_accumulate {
   using R = typename P::R;
   const Scalars *sc = d.sc;
   if (!sc->label_run) return;
+  __shared__ KeySums<NACC, 16> comp;
+  key_sums_init(comp);
   const bool ok = sc->nnew <= d.max_bubbles && sc->nfree >= sc->nnew;
   const int n = sc->n_lab;
   for (int base = bk.id * blockDim.x; base < n; base += bk.n * blockDim.x) {
@@ -1942,8 +1982,9 @@ struct K_label_accumulate {
       }
       d.lab[i] = -1;
     }
-    wave_add_by_key<NACC>(key, v, d.c_acc, SUB, bk.id % SUB);
+    wave_add_by_key_lds(key, v, comp, d.c_acc, SUB, bk.id % SUB, NACC, 0);
   }
+  key_sums_flush(comp, d.c_acc, SUB, bk.id % SUB, NACC, 0);
 }
 };
 

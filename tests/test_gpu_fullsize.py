@@ -28,9 +28,10 @@ HORIZON = 4000
 # populations, w_a rho: a PDF therefore carries an absolute error of a few
 # ulp of w_a, whatever its own size (a reconstructed population can come
 # out far below w_a), and agrees to 1e-5 relative to max(|f|, w_a).  Fill
-# levels and masses (order one) agree to 1e-5 absolute.  Bubble volumes are exact sums of the fill levels (order 1e3
-# cells per bubble): 1e-6 relative; V* and p follow them.  The total mass is
-# the FP64 sum of FP32 cell values: 1e-7 relative.
+# levels and masses (order one) agree to 1e-5 absolute.  Bubble volumes are
+# exact sums of the fill levels (order 1e3 cells per bubble): 1e-6
+# relative; V* and p follow them.  The total mass is the FP64 sum of FP32
+# cell values: 1e-7 relative.
 TOL_F = 1e-5
 W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
 # Two discrete choices of an interface cell are taken on its normal n, in
