@@ -1820,7 +1820,9 @@ struct K_label_union {
       const bool dup = lane > 0 && pli == li && plj == lj;
       // outside the set, one tree already, or left to the left lane
       if (lj < 0 || lj == li || dup) continue;
-      uf_union(d.lab, (int)i, (int)j);
+      // from the labels already read (each lies in its cell's tree:
+      // labels only decrease towards the roots)
+      uf_union(d.lab, li, lj);
     }
   }
 }
