@@ -1812,16 +1812,23 @@ struct K_label_union {
     int x = 0, y = 0, z = 0;
     if (ok) coords(d, i, x, y, z);
     const int li = ok ? d.lab[i] : -1;
+    // the neighbours' labels first, all at once (a label read before
+    // other unions still lies in its cell's tree: labels only decrease
+    // towards the roots)
+    int ln[Q / 2];
 #pragma unroll
-    for (int a = 1; a < Q; a += 2) {
+    for (int q = 0; q < Q / 2; ++q) {
+      const int a = 2 * q + 1;
       const long long j = ok ? nbr_checked(d, x, y, z, CX[a], CY[a], CZ[a]) : -1;
-      const int lj = j >= 0 ? d.lab[j] : -1;
+      ln[q] = j >= 0 ? d.lab[j] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < Q / 2; ++q) {
+      const int lj = ln[q];
       const int pli = __shfl_up(li, 1, 64), plj = __shfl_up(lj, 1, 64);
       const bool dup = lane > 0 && pli == li && plj == lj;
       // outside the set, one tree already, or left to the left lane
       if (lj < 0 || lj == li || dup) continue;
-      // from the labels already read (each lies in its cell's tree:
-      // labels only decrease towards the roots)
       uf_union(d.lab, li, lj);
     }
   }
@@ -1855,11 +1862,19 @@ struct K_label_roots {
     if ((d.flag_dst[i] & TYPE_MASK) == T_INLET) atomicOr(&d.aux2[r], 1);
     int x, y, z;
     coords(d, i, x, y, z);
-    for (int a = 1; a < Q; a += 2) {
+    // the neighbours' slots first, all at once (set membership and slots
+    // do not change in this pass)
+    int sn[Q / 2];
+#pragma unroll
+    for (int q = 0; q < Q / 2; ++q) {
+      const int a = 2 * q + 1;
       const long long j = nbr_checked(d, x, y, z, CX[a], CY[a], CZ[a]);
-      if (j < 0 || d.lab[j] < 0) continue;
-      const int sj = d.bslot[j];
-      if (sj == s) continue;
+      sn[q] = (j < 0 || d.lab[j] < 0) ? -1 : d.bslot[j];
+    }
+#pragma unroll
+    for (int q = 0; q < Q / 2; ++q) {
+      const int sj = sn[q];
+      if (sj < 0 || sj == s) continue;
       atomicOr(&d.aux2[r], 4);
       atomicMin(&d.b_rmin[s], r);
       atomicMax(&d.b_rmax[s], r);
