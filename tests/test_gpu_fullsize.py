@@ -79,11 +79,11 @@ def _free(*objs):
     torch.cuda.empty_cache()
 
 
-def _bench_domain(sc):
-    """A domain as the benchmark builds it, with the window's phase timing
-    switched on once the warm-up is done (see `_advance`)."""
+def _bench_domain(sc, precision="fp32"):
+    """A domain as the benchmark builds it (FP32 there), with the window's
+    phase timing switched on once the warm-up is done (see `_advance`)."""
     from paper_1604_01632_amd import Domain
-    return Domain.from_scene(sc, "fp32")
+    return Domain.from_scene(sc, precision)
 
 
 def _advance(d, to_step: int) -> None:
@@ -190,16 +190,9 @@ def _compare_fp32_step(do, bo, so, dg, bg, sg, N, eps, audit):
     assert so["step"] == sg["step"] and so["next_id"] == sg["next_id"]
 
 
-@pytest.mark.timeout(900)
-def test_p1_topology_step_fp32_in_benchmark_window(p1):
-    """A step with a topology change inside the benchmark's timed window
-    (FP32, 256^3, benchmark launch configuration): the oracle takes over
-    the state the GPU held before that step and runs it; cell types, bubble
-    IDs and the bubble table agree exactly, the fields within FP32 rounding.
-    The GPU path is deterministic, so the run that finds the step and the
-    run that is compared reach the same state."""
-    oracle = _oracle()
-    g = _bench_domain(p1)
+def _first_topology_step(sc, precision):
+    """The first step after the warm-up whose labelling creates bubbles."""
+    g = _bench_domain(sc, precision)
     _advance(g, WARMUP)
     t0 = g.read(())["scalars"]["n_topology"]
     t_star = None
@@ -210,9 +203,24 @@ def test_p1_topology_step_fp32_in_benchmark_window(p1):
             break
     _free(g)
     assert t_star is not None, "no topology change within 600 steps of the window start"
-    say(f"[fullsize] p1 fp32: first topology change of the window at step {t_star}")
+    return t_star
 
-    g = _bench_domain(p1)
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_p1_topology_step_in_benchmark_window(p1, precision):
+    """A step with a topology change inside the benchmark's timed window
+    (256^3, benchmark launch configuration): the oracle takes over the
+    state the GPU held before that step and runs it.  FP64: everything
+    bit for bit.  FP32 (the benchmark's form): cell types, bubble IDs and
+    the bubble table exact, the fields within FP32 rounding.  The GPU path
+    is deterministic, so the run that finds the step and the run that is
+    compared reach the same state."""
+    oracle = _oracle()
+    t_star = _first_topology_step(p1, precision)
+    say(f"[fullsize] p1 {precision}: first topology change of the window at step {t_star}")
+
+    g = _bench_domain(p1, precision)
     _advance(g, t_star - 1)
     before = g.read()
     bb, sb = g.bubbles(), before["scalars"]
@@ -229,15 +237,21 @@ def test_p1_topology_step_fp32_in_benchmark_window(p1):
     audit.t_before = t_before
     o.step(1)
     g.step(1)
-    dg = g.read()
-    bg, sg = g.bubbles(), dg["scalars"]
-    assert sg["n_topology"] == sb["n_topology"] + 1
-    do, bo, so = o.read(), o.bubbles(), o.scalars()
-    assert so["n_topology"] == 1, "the oracle saw no topology change in this step"
-    say(f"[fullsize] p1 fp32 step {t_star}: bubbles {len(bb['id'])} -> {len(bg['id'])}, "
-        f"next ID {sb['next_id']} -> {sg['next_id']}")
-    _compare_fp32_step(do, bo, so, dg, bg, sg, p1.n, p1.params().get("eps_convert", 1e-2),
-                       audit)
+    assert o.scalars()["n_topology"] == 1, "the oracle saw no topology change in this step"
+    if precision == "fp64":
+        assert g.read(())["scalars"]["n_topology"] == sb["n_topology"] + 1
+        compare_state(o, g, f"p1 fp64 step {t_star}", exact=True)
+        say(f"[fullsize] p1 fp64 step {t_star}: bitwise equal, bubbles {len(bb['id'])} -> "
+            f"{len(g.bubbles()['id'])}")
+    else:
+        dg = g.read()
+        bg, sg = g.bubbles(), dg["scalars"]
+        assert sg["n_topology"] == sb["n_topology"] + 1
+        do, bo, so = o.read(), o.bubbles(), o.scalars()
+        say(f"[fullsize] p1 fp32 step {t_star}: bubbles {len(bb['id'])} -> {len(bg['id'])}, "
+            f"next ID {sb['next_id']} -> {sg['next_id']}")
+        _compare_fp32_step(do, bo, so, dg, bg, sg, p1.n, p1.params().get("eps_convert", 1e-2),
+                           audit)
     _free(g, o)
 
 
