@@ -115,3 +115,102 @@ def test_oracle_fsum_matches_math_fsum(oracle_lib):
         cases.append(c)
     for c in cases:
         assert oracle_lib.fsum(c) == math.fsum(c), c[:4]
+
+
+# The interface cells' gas volumes 1 - phi travel through the gather kernel
+# as three chunks of (1 - phi) 2^53 (exact whenever phi lies in (-1, 3))
+# and are joined to the exact-sum words afterwards; other values go to the
+# exact-sum words directly.  This harness restates that reduction on the
+# host with the constants of device.hpp and returns the joined sum.
+CHUNK_HARNESS = r"""
+#include <cmath>
+#include <cstdio>
+#include <cstdint>
+#include <cstring>
+#include "exactsum.hpp"
+using namespace fslbm;
+int main() {
+  int n;
+  while (std::scanf("%d", &n) == 1) {
+    long long acc[EX_WORDS] = {0}, ch[3] = {0, 0, 0};
+    int inexact = 0;
+    for (int k = 0; k < n; ++k) {
+      unsigned long long bits;
+      std::scanf("%llx", &bits);
+      double phi;
+      std::memcpy(&phi, &bits, 8);
+      const double gv = 1.0 - phi;
+      if (std::fabs(gv) < 2.0) {
+        const long long q = (long long)(gv * 0x1p53);
+        if (std::ldexp((double)q, -FIX_SCALE) != gv) inexact = 1;
+        const long long lo = (1ll << FIX_BITS) - 1;
+        ch[0] += (int)(q & lo);
+        ch[1] += (int)((q >> FIX_BITS) & lo);
+        ch[2] += (int)(q >> (2 * FIX_BITS));
+      } else {
+        ExTerm t = ex_split(gv);
+        for (int c = 0; c < EX_WORDS; ++c) acc[c] += t.w[c];
+      }
+    }
+    for (int c = 0; c < 3; ++c) {
+      ExTerm t = ex_split(std::ldexp((double)ch[c], FIX_BITS * c - FIX_SCALE));
+      for (int w = 0; w < EX_WORDS; ++w) acc[w] += t.w[w];
+    }
+    double r = ex_value(acc);
+    unsigned long long o;
+    std::memcpy(&o, &r, 8);
+    std::printf("%016llx %d\n", o, inexact);
+  }
+  return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def chunk_harness(tmp_path_factory):
+    import re
+    text = open(os.path.join(CSRC, "device.hpp")).read()
+    bits = re.search(r"constexpr int VA_FIX_BITS = (\d+);", text).group(1)
+    scale = re.search(r"constexpr int VA_FIX_SCALE = (\d+);", text).group(1)
+    d = tmp_path_factory.mktemp("chunks")
+    src = d / "c.cpp"
+    src.write_text(CHUNK_HARNESS)
+    exe = d / "c"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", f"-I{CSRC}",
+                    f"-DFIX_BITS={bits}", f"-DFIX_SCALE={scale}", str(src), "-o", str(exe)],
+                   check=True)
+    return str(exe)
+
+
+def test_volume_chunks_are_exact(chunk_harness):
+    """Sec. 2.3 volumes: the chunked sum of 1 - phi equals math.fsum of the
+    same terms for FP64 and FP32 fill levels anywhere in (-1, 3), including
+    levels next to 0 and 1 (where 1 - phi is tiny or exactly 1), and for
+    levels outside that range (the exact-sum fallback)."""
+    rng = random.Random(3)
+    f32 = lambda v: struct.unpack("<f", struct.pack("<f", v))[0]  # noqa: E731
+    cases = []
+    for k in range(300):
+        n = rng.randint(1, 400)
+        kind = k % 6
+        if kind == 0:
+            c = [rng.uniform(-0.1, 1.1) for _ in range(n)]
+        elif kind == 1:
+            c = [f32(rng.uniform(-0.1, 1.1)) for _ in range(n)]
+        elif kind == 2:
+            c = [1.0 - rng.random() * 2.0 ** rng.randint(-60, -1) for _ in range(n)]
+        elif kind == 3:
+            c = [rng.choice([1, -1]) * rng.random() * 2.0 ** rng.randint(-80, -1) for _ in range(n)]
+        elif kind == 4:
+            c = [rng.uniform(-0.999999, 2.999999) for _ in range(n)]
+        else:
+            c = [rng.uniform(-1, 1) * 10.0 ** rng.randint(0, 8) for _ in range(n)]
+        cases.append(c)
+    inp = "".join(f"{len(c)} " + " ".join(_hex(v) for v in c) + "\n" for c in cases)
+    out = subprocess.run([chunk_harness], input=inp, capture_output=True, text=True,
+                         check=True).stdout.split("\n")
+    for c, line in zip(cases, out):
+        h, inexact = line.split()
+        got = struct.unpack("<d", struct.pack("<Q", int(h, 16)))[0]
+        assert inexact == "0"
+        assert got == math.fsum(1.0 - v for v in c)
