@@ -714,17 +714,18 @@ __device__ __forceinline__ int wave_append(bool pred, int *counter) {
   return base + (int)__popcll(m & ((1ull << lane) - 1ull));
 }
 
-// Claims cell j once per step (bit j of the mark field); true for the
-// first caller.
-__device__ __forceinline__ bool claim_cell(const Dev &d, long long j) {
-  const unsigned bit = 1u << (8 * (unsigned)(j & 3));
-  const unsigned old = atomicOr(&d.mark[j >> 2], bit);
-  return (old & bit) == 0;
+// A cell is claimed once per step: one byte of the mark field per cell,
+// its low bit set by the first caller.
+__device__ __forceinline__ unsigned claim_bit(long long j) { return 1u << (8 * (unsigned)(j & 3)); }
+
+// Sets the claim bit of cell j and returns its word as it was before: the
+// claim is won when claim_bit(j) was clear in it.
+__device__ __forceinline__ unsigned claim_cell(const Dev &d, long long j) {
+  return atomicOr(&d.mark[j >> 2], claim_bit(j));
 }
 
 __device__ __forceinline__ void release_cell(const Dev &d, long long j) {
-  const unsigned bit = 1u << (8 * (unsigned)(j & 3));
-  atomicAnd(&d.mark[j >> 2], ~bit);
+  atomicAnd(&d.mark[j >> 2], ~claim_bit(j));
 }
 
 // ---------------------------------------------------------------- k_bulk
@@ -1032,14 +1033,24 @@ struct K_conv_types {
     // wave
     uint32_t won = 0;
     if (F || E) {
+      // every claim in flight before any answer is looked at
+      uint32_t want = 0;
+      unsigned got[Q];
 #pragma unroll
       for (int a = 1; a < Q; ++a) {
         const uint8_t tj = fsn[a] & TYPE_MASK;
+        got[a] = 0;
         if ((F && tj == T_GAS) || (E && tj == T_LIQ)) {
           const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
           d.flag_dst[j] = (uint8_t)((fdn[a] & ~TYPE_MASK) | T_IFACE);
-          if (claim_cell(d, j)) won |= 1u << a;
+          got[a] = claim_cell(d, j);
+          want |= 1u << a;
         }
+      }
+#pragma unroll
+      for (int a = 1; a < Q; ++a) {
+        const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
+        if (((want >> a) & 1u) && !(got[a] & claim_bit(j))) won |= 1u << a;
       }
     }
     const int cnt = __popc(won);
