@@ -1303,14 +1303,19 @@ struct K_excess {
       }
     } else if (t == T_LIQ && tn == T_IFACE) {
       // a new gas-region cell: a merge if its gas-region neighbours carry
-      // another bubble
+      // another bubble (their slots read all at once first)
       const int s = slot;
+      int sn[Q];
+#pragma unroll
+      for (int a = 1; a < Q; ++a)
+        sn[a] = in_gas_region(fn[a] & TYPE_MASK) ? d.bslot[nbr(d, x, y, z, CX[a], CY[a], CZ[a])]
+                                                  : s;
+#pragma unroll
       for (int a = 1; a < Q; ++a) {
-        const long long j = nbr(d, x, y, z, CX[a], CY[a], CZ[a]);
-        if (in_gas_region(fn[a] & TYPE_MASK) && d.bslot[j] != s) {
+        if (sn[a] != s) {
           trig = true;
           atomicOr(&d.b_affect[s], 1);
-          atomicOr(&d.b_affect[d.bslot[j]], 1);
+          atomicOr(&d.b_affect[sn[a]], 1);
         }
       }
     }
