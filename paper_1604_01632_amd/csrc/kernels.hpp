@@ -613,6 +613,9 @@ struct K_geom {
     const int k = xcd_chunk(c, m) * THREADS + (int)threadIdx.x;
     if (k >= n) continue;
     const long long i = d.ilist_src[k];
+    // the bubble pressure in the same rounds as the fill levels
+    const int slot = d.bslot[i];
+    const double bp = d.b_p[slot];
     int x, y, z;
     coords(d, i, x, y, z);
     const PhiWin<R> W(d, x, y, z);
@@ -657,13 +660,12 @@ struct K_geom {
       }
       kappa = sum / (R)cnt;
     }
-    const int slot = d.bslot[i];
     R g;
     if constexpr (P::EXACT) {
-      const R p_gas = (R)d.b_p[slot] + (R)2.0 * (R)d.sigma * kappa;
+      const R p_gas = (R)bp + (R)2.0 * (R)d.sigma * kappa;
       g = (R)3.0 * p_gas;  // rho_gas, p = rho cs^2
     } else {
-      g = (R)(3.0 * d.b_p[slot] - 1.0) + (R)6 * (R)d.sigma * kappa;  // rho_gas - 1
+      g = (R)(3.0 * bp - 1.0) + (R)6 * (R)d.sigma * kappa;  // rho_gas - 1
     }
     const R nn = an[0] + an[1] + an[2];
     uint32_t mask = 0;
@@ -1861,25 +1863,12 @@ struct K_label_roots {
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   if (!d.sc->label_run) return;
   FSLBM_LABEL_SET(i) {
-    int r = (int)i, p = d.lab[i];
-    while (p != r) {
-      r = p;
-      p = d.lab[r];
-    }
-    d.lab[i] = r;
+    // the cell's own values and its neighbours' slots are read while the
+    // root is found (set membership and slots do not change in this pass)
     const int s = d.bslot[i];
-    if (r == (int)i) {
-      atomicMin(&d.b_rmin[s], r);
-      atomicMax(&d.b_rmax[s], r);
-      // the roots are listed (the new-cell list is free during labelling)
-      const int q = atomicAdd(&d.sc->n_roots, 1);
-      if (q < (int)d.N) d.nlist[q] = r;
-    }
-    if ((d.flag_dst[i] & TYPE_MASK) == T_INLET) atomicOr(&d.aux2[r], 1);
+    const bool inlet = (d.flag_dst[i] & TYPE_MASK) == T_INLET;
     int x, y, z;
     coords(d, i, x, y, z);
-    // the neighbours' slots first, all at once (set membership and slots
-    // do not change in this pass)
     int sn[Q / 2];
 #pragma unroll
     for (int q = 0; q < Q / 2; ++q) {
@@ -1887,6 +1876,20 @@ struct K_label_roots {
       const long long j = nbr_checked(d, x, y, z, CX[a], CY[a], CZ[a]);
       sn[q] = (j < 0 || d.lab[j] < 0) ? -1 : d.bslot[j];
     }
+    int r = (int)i, p = d.lab[i];
+    while (p != r) {
+      r = p;
+      p = d.lab[r];
+    }
+    d.lab[i] = r;
+    if (r == (int)i) {
+      atomicMin(&d.b_rmin[s], r);
+      atomicMax(&d.b_rmax[s], r);
+      // the roots are listed (the new-cell list is free during labelling)
+      const int q = atomicAdd(&d.sc->n_roots, 1);
+      if (q < (int)d.N) d.nlist[q] = r;
+    }
+    if (inlet) atomicOr(&d.aux2[r], 1);
 #pragma unroll
     for (int q = 0; q < Q / 2; ++q) {
       const int sj = sn[q];
@@ -1994,12 +1997,18 @@ struct K_label_accumulate {
     for (int c = 0; c < NACC; ++c) v[c] = 0;
     if (k < n) {
       const long long i = d.clist[k];
+      // every value the cell may need, in two rounds (a set cell has a
+      // root and a slot)
       const int r = d.lab[i];
-      if (ok && (d.aux2[r] & 2)) {
-        key = d.aux0[r];
-        const uint8_t t = d.flag_dst[i] & TYPE_MASK;
-        const double w = t == T_IFACE ? 1.0 - (double)((const R *)d.phi_dst)[i] : 1.0;
-        const double ratio = d.b_ratio[d.bslot[i]];
+      const uint8_t t = d.flag_dst[i] & TYPE_MASK;
+      const R ph = ((const R *)d.phi_dst)[i];
+      const int sl = d.bslot[i];
+      const int a2 = d.aux2[r], a0 = d.aux0[r];
+      const double rt = d.b_ratio[sl];
+      if (ok && (a2 & 2)) {
+        key = a0;
+        const double w = t == T_IFACE ? 1.0 - (double)ph : 1.0;
+        const double ratio = rt;
         const double ws = ratio >= 0.0 ? ratio * w : -ratio;
         const ExTerm tw = ex_split(w), ts = ex_split(ws);
 #pragma unroll
