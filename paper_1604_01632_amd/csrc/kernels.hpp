@@ -1487,6 +1487,7 @@ struct K_list_fill {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   __shared__ int wsum[4];
+  const int tile_base = d.tileoff[bk.id];  // in the same round as the flags
   const long long i0 = (long long)bk.id * LTILE + 16 * (long long)threadIdx.x;
   const uint32_t bits = i0 < d.N ? iface_bits16(d, i0) : 0u;
   const int c = __popc(bits);
@@ -1503,7 +1504,7 @@ struct K_list_fill {
   __syncthreads();
   int before = 0;
   for (int k = 0; k < w; ++k) before += wsum[k];
-  int pos = d.tileoff[bk.id] + before + incl - c;
+  int pos = tile_base + before + incl - c;
   for (int b = 0; b < 16; ++b) {
     if ((bits >> b) & 1u) {
       const long long i = i0 + b;
