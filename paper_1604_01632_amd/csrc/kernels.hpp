@@ -566,12 +566,28 @@ struct PhiWin {
 // the cell already in registers (B[dz][dy][dx]); same sums, same order.
 template <int DD, class R>
 __device__ __forceinline__ R height_curvature_cached(const Dev &d, const R *phi,
-                                                     const PhiWin<R> &W, const R (&B)[3][3][3]) {
+                                                     const PhiWin<R> &W, const R (&B)[3][3][3],
+                                                     int x, bool rows) {
   R H[3][3];
 #pragma unroll
   for (int a = -1; a <= 1; ++a)
 #pragma unroll
     for (int b = -1; b <= 1; ++b) {
+      // along x with plain rows: x-3, x-2 and x+2, x+3 from two loads
+      R ext[4];
+      if constexpr (DD == 0 && sizeof(R) == 4) {
+        if (rows) {
+          const R *rp = phi + (long long)d.nx * (W.yp[a + 3] + (long long)d.ny * W.zp[b + 3]) + x;
+          float4 lo;
+          float2 hi;
+          __builtin_memcpy(&lo, rp - 3, 16);
+          __builtin_memcpy(&hi, rp + 2, 8);
+          ext[0] = lo.x;
+          ext[1] = lo.y;
+          ext[2] = hi.x;
+          ext[3] = hi.y;
+        }
+      }
       R s = (R)0;
 #pragma unroll
       for (int k = -3; k <= 3; ++k) {
@@ -580,6 +596,7 @@ __device__ __forceinline__ R height_curvature_cached(const Dev &d, const R *phi,
         const int oz = DD == 2 ? k : b;
         R v;
         if (k >= -1 && k <= 1) v = B[oz + 1][oy + 1][ox + 1];
+        else if (DD == 0 && sizeof(R) == 4 && rows) v = ext[k < 0 ? k + 3 : k];
         else v = W.get(d, phi, ox, oy, oz);
         s += v;
       }
@@ -620,12 +637,29 @@ struct K_geom {
     coords(d, i, x, y, z);
     const PhiWin<R> W(d, x, y, z);
     R B[3][3][3];
+    // plain rows (no walls, x-3..x+3 inside the box) of 4-byte levels: each
+    // x-row of the block is one 16-byte load
+    const bool rows = sizeof(R) == 4 && !d.has_walls && x >= 3 && x + 3 < d.nx;
+    if (rows) {
 #pragma unroll
-    for (int dz = -1; dz <= 1; ++dz)
+      for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
+        for (int dy = -1; dy <= 1; ++dy) {
+          const R *rp = phi + (long long)d.nx * (W.yp[dy + 3] + (long long)d.ny * W.zp[dz + 3]) + x;
+          float4 v;
+          __builtin_memcpy(&v, rp - 1, 16);
+          B[dz + 1][dy + 1][0] = v.x;
+          B[dz + 1][dy + 1][1] = v.y;
+          B[dz + 1][dy + 1][2] = v.z;
+        }
+    } else {
 #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) B[dz + 1][dy + 1][dx + 1] = W.get(d, phi, dx, dy, dz);
+      for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) B[dz + 1][dy + 1][dx + 1] = W.get(d, phi, dx, dy, dz);
+    }
     R nv[3] = {(R)0, (R)0, (R)0};
 #pragma unroll
     for (int p = -1; p <= 1; ++p)
@@ -647,15 +681,15 @@ struct K_geom {
       R sum = (R)0;
       int cnt = 0;
       if (an[0] >= thr) {
-        sum += height_curvature_cached<0>(d, phi, W, B);
+        sum += height_curvature_cached<0>(d, phi, W, B, x, rows);
         ++cnt;
       }
       if (an[1] >= thr) {
-        sum += height_curvature_cached<1>(d, phi, W, B);
+        sum += height_curvature_cached<1>(d, phi, W, B, x, rows);
         ++cnt;
       }
       if (an[2] >= thr) {
-        sum += height_curvature_cached<2>(d, phi, W, B);
+        sum += height_curvature_cached<2>(d, phi, W, B, x, rows);
         ++cnt;
       }
       kappa = sum / (R)cnt;
