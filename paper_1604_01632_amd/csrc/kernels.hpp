@@ -1745,9 +1745,24 @@ struct K_label_init {
         for (int q = 0; q < 16; ++q)
           tt[q] = i0 + q < d.N ? (uint8_t)(d.flag_dst[i0 + q] & TYPE_MASK) : (uint8_t)T_WALL;
       }
+      uint32_t gas = 0;
 #pragma unroll
       for (int q = 0; q < 16; ++q)
-        if (in_gas_region(tt[q]) && (all || d.b_affect[d.bslot[i0 + q]])) bits |= 1u << q;
+        if (in_gas_region(tt[q])) gas |= 1u << q;
+      if (all || !gas) {
+        bits = gas;
+      } else if (i0 + 16 <= d.N) {
+        // the 16 slots with four 16-byte loads (i0 is a multiple of 16)
+        int sl[16];
+        __builtin_memcpy(sl, d.bslot + i0, 64);
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (((gas >> q) & 1u) && d.b_affect[sl[q]]) bits |= 1u << q;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (((gas >> q) & 1u) && d.b_affect[d.bslot[i0 + q]]) bits |= 1u << q;
+      }
     }
     // the whole tile outside the set: nothing to do
     if (!__syncthreads_or(bits != 0u)) continue;
