@@ -76,3 +76,21 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(pkg, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         pkg.lib()
+
+
+def test_workspace_bytes_at_the_size_limit(binding):
+    """Cell indices are 32-bit: a box of 2^31 - 1 cells or fewer is sized
+    (per cell at least the two lattices), one of 2^31 or more is rejected;
+    the three precisions order as their storage does."""
+    import scenes
+    base = scenes.config("c1").params()
+    big = dict(base, nx=1290, ny=1290, nz=1290)  # 2 146 689 000 cells
+    n = 1290 ** 3
+    sizes = {}
+    for prec, s in ((0, 8), (1, 4), (2, 2)):
+        b = binding.fslbm_workspace_bytes(dict(big, precision=prec))
+        assert b >= 2 * 19 * s * n
+        sizes[prec] = b
+    assert sizes[0] > sizes[1] > sizes[2]
+    assert binding.fslbm_workspace_bytes(dict(base, nx=2048, ny=1024, nz=1024)) == 0  # 2^31
+    assert binding.fslbm_workspace_bytes(dict(base, nx=2048, ny=2048, nz=2048)) == 0
