@@ -92,12 +92,20 @@ def test_orifice_injection():
 
 
 def test_flat_interface_and_all_liquid_edge_cases():
+    """Degenerate scenes: a flat interface sliding in a periodic box, an
+    all-liquid box, a one-cell-wide line and an all-gas box."""
     spec = [(GAS, 0.0, 0)] * 3 + [(IFACE, 0.5, 0)] + [(LIQ, 1.0, -1)] * 6 + [(IFACE, 0.5, 0)] + [(GAS, 0.0, 0)] * 3
     run_pair(scenes.layers(spec, ny=5, nz=4, velocity=(0.0, 0.04, -0.03), tau=0.7), 10, 5, "flat-slide")
     liq = scenes.spheres(n=(9, 7, 5), centers=(), radii=(), rho_l=1.0)
     run_pair(liq, 10, 5, "all-liquid")
     one = scenes.spheres(n=(1, 12, 1), centers=(), radii=(), rho_l=1.0)
     run_pair(one, 6, 3, "line")
+    # no fluid at all: empty interface, candidate and new-cell lists, one
+    # bubble made of gas cells only (total mass 0, bucket spread over no
+    # interface cell)
+    gas = scenes.layers([(GAS, 0.0, 0)] * 6, ny=5, nz=4)
+    o, _ = run_pair(gas, 6, 3, "all-gas")
+    assert o.bubbles()["volume"].tolist() == [120.0] and o.scalars()["total_mass"] == 0.0
 
 
 def test_trigger_equals_labelling_every_step():
