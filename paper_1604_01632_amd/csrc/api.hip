@@ -217,11 +217,16 @@ LaunchCfg make_cfg(const fslbm_params &p, int bulk_threads = 256) {
   };
   cfg.bulk_threads = bulk_threads;
   cfg.blocks[G_BULK] = (int)((N + bulk_threads - 1) / bulk_threads);
-  cfg.blocks[G_LIST] = clampb(256, 2048);
-  cfg.blocks[G_SMALL] = clampb(256, 256);
+  // The list and labelling kernels walk lists a few per cent of the cells
+  // long with grid-stride loops: one block per 2048 or 4096 cells is ample,
+  // and a block that finds no work still costs its dispatch (a batch of
+  // small domains would otherwise launch hundreds of thousands of them).
+  // Large boxes reach the caps.
+  cfg.blocks[G_LIST] = clampb(2048, 2048);
+  cfg.blocks[G_SMALL] = clampb(4096, 256);
   cfg.blocks[G_TILE] = (int)((N + 4095) / 4096);
   cfg.blocks[G_ONE] = 1;
-  cfg.blocks[G_CELL] = clampb(256, 1024);
+  cfg.blocks[G_CELL] = clampb(4096, 1024);
   cfg.with_mass = 1;
   return cfg;
 }
