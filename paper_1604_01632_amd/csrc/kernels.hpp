@@ -637,9 +637,15 @@ struct K_geom {
     coords(d, i, x, y, z);
     const PhiWin<R> W(d, x, y, z);
     R B[3][3][3];
-    // plain rows (no walls, x-3..x+3 inside the box) of 4-byte levels: each
-    // x-row of the block is one 16-byte load
-    const bool rows = sizeof(R) == 4 && !d.has_walls && x >= 3 && x + 3 < d.nx;
+    // plain rows of 4-byte levels: each x-row of the block is one 16-byte
+    // load where every sample of those rows is an ordinary cell - x-3..x+3
+    // without a periodic wrap, and off the wall layers (walls only form the
+    // faces of non-periodic axes) for x-3..x+3 and the rows y-1..y+1,
+    // z-1..z+1
+    const bool xin = d.per[0] ? (x >= 3 && x + 3 < d.nx) : (x >= 4 && x + 4 < d.nx);
+    const bool yin = d.per[1] || (y >= 2 && y + 2 < d.ny);
+    const bool zin = d.per[2] || (z >= 2 && z + 2 < d.nz);
+    const bool rows = sizeof(R) == 4 && xin && yin && zin;
     if (rows) {
 #pragma unroll
       for (int dz = -1; dz <= 1; ++dz)

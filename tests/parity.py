@@ -118,3 +118,98 @@ def run_pair(sc, steps: int, every: int, name: str, precision="fp64", **over):
     say(f"[parity] {name}: ok ({'bitwise' if exact else 'within tolerance'}); worst {', '.join(f'{k}={v:.1e}' for k, v in worst.items())}; "
         f"topology changes {s['n_topology']}, bubbles {len(o.bubbles()['id'])}")
     return o, g
+
+
+# One FP32 step from an FP32-representable state against the FP64 oracle.
+# Every stored value is the result of a few dozen FP32 operations (unit
+# roundoff 2^-24 = 6e-8) on terms of the size of the equilibrium
+# populations, w_a rho: a PDF therefore carries an absolute error of a few
+# ulp of w_a, whatever its own size (a reconstructed population can come
+# out far below w_a), and agrees to 1e-5 relative to max(|f|, w_a).  Fill
+# levels and masses (order one) agree to 1e-5 absolute.  Bubble volumes are
+# exact sums of the fill levels (order 1e3 cells per bubble): 1e-6
+# relative; V* and p follow them.  The total mass is the FP64 sum of FP32
+# cell values: 1e-7 relative.
+TOL_F = 1e-5
+W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+# Two discrete choices of an interface cell are taken on its normal n, in
+# the precision of the form: which directions are reconstructed (c_a.n > 0)
+# and the dominant axis of the height function.  Each component of n is a
+# sum of 18 terms of size at most 4 |phi| (phi <= 1.1), so in FP32 it is off
+# by at most about 18 * 2^-24 * 4.4 * 18 = 8.5e-5 in the worst case, and
+# c_a.n or the gap between two |n_k| by twice that: within that band of a
+# tie the FP32 form may choose the other way.  Only such a cell may hold
+# PDFs beyond TOL_F (its other values are bounded as usual).
+TIE_BAND = 2e-4
+TOL_FIELD = 1e-5
+TOL_BUBBLE = 1e-6
+TOL_MASS32 = 1e-7
+
+
+def near_tie(i, t_before, normal, c, shape):
+    """Smallest distance of an FP64 decision of interface cell i from its
+    tie: |c_a.n| over the directions whose source cell is interface or
+    liquid, and the gap between the two largest |n_k|."""
+    nz, ny, nx = shape
+    n = normal[:, i]
+    x, y, z = i % nx, (i // nx) % ny, i // (nx * ny)
+    d = np.inf
+    for a in range(1, 19):
+        sx, sy, sz = (x - c[a, 0]) % nx, (y - c[a, 1]) % ny, (z - c[a, 2]) % nz
+        if t_before[sx + nx * (sy + ny * sz)] in (IFACE, LIQ):
+            d = min(d, abs(float(c[a] @ n)))
+    an = np.sort(np.abs(n))
+    return min(d, float(an[2] - an[1]))
+
+
+def compare_fp32_step(do, bo, so, dg, bg, sg, N, eps, audit):
+    to, tg = do["cell_type"], dg["cell_type"]
+    bad = np.nonzero(to != tg)[0]
+    if bad.size:
+        ph = do["phi"][bad]
+        margin = np.minimum(np.abs(ph - (1 + eps)), np.abs(ph + eps))
+        raise AssertionError(f"{bad.size} cell types differ, e.g. {bad[:5].tolist()}; "
+                             f"min threshold margin {margin.min():.3e}")
+    assert np.array_equal(do["bubble_id"], dg["bubble_id"]), "bubble IDs differ"
+    fl = (to == IFACE) | (to == LIQ)
+    cells = np.nonzero(fl)[0]
+    fo, fg = do["f"].reshape(19, N), dg["f"].reshape(19, N)
+    rel_f, worst, beyond = 0.0, None, np.zeros(cells.size, bool)
+    for a in range(19):
+        x, y = fo[a, fl], fg[a, fl]
+        assert np.all(x > 0)
+        e = np.abs(y - x) / np.maximum(x, W[a])
+        beyond |= e > TOL_F
+        e[beyond] = 0.0  # judged by the audit below
+        k = int(np.argmax(e))
+        if e[k] > rel_f:
+            rel_f, worst = float(e[k]), (a, int(cells[k]), float(x[k]), float(y[k]))
+    if worst is not None:
+        a, i, x, y = worst
+        say(f"[fp32 step] worst PDF within the bound: direction {a}, cell {i}, oracle {x:.9e}, "
+            f"gpu {y:.9e}")
+    odd = cells[beyond]
+    ties = [audit(int(i)) for i in odd]
+    say(f"[fp32 step] {odd.size} cell(s) with PDFs beyond {TOL_F:g}: types at t "
+        f"{sorted(set(int(audit.t_before[i]) for i in odd))}, distance of an FP64 choice "
+        f"from its tie at most {max(ties, default=0.0):.2e}")
+    assert all(audit.t_before[i] == IFACE for i in odd)
+    assert max(ties, default=0.0) <= TIE_BAND, "PDFs differ at a cell with no near-tie choice"
+    assert odd.size <= max(1, cells.size // 100000)
+    it = to == IFACE
+    err = {k: float(np.max(np.abs(do[k][it] - dg[k][it]))) for k in ("phi", "mass")}
+    assert bo["id"].tolist() == bg["id"].tolist(), "bubble IDs of the table differ"
+    assert bo["n_cells"].tolist() == bg["n_cells"].tolist(), "bubble cell counts differ"
+    assert bo["flags"].tolist() == bg["flags"].tolist()
+    berr = {k: float(np.max(np.abs(bo[k] - bg[k]) / np.abs(bo[k]))) for k in
+            ("volume", "v_star", "pressure")}
+    merr = abs(so["total_mass"] - sg["total_mass"]) / abs(so["total_mass"])
+    say(f"[fp32 step] fp32 step vs oracle: f {rel_f:.2e}, phi {err['phi']:.2e}, mass "
+        f"{err['mass']:.2e}, bubbles {', '.join(f'{k} {v:.2e}' for k, v in berr.items())}, "
+        f"total mass {merr:.2e}")
+    assert rel_f <= TOL_F
+    assert err["phi"] <= TOL_FIELD and err["mass"] <= TOL_FIELD
+    for v in berr.values():
+        assert v <= TOL_BUBBLE
+    assert merr <= TOL_MASS32
+    assert so["step"] == sg["step"] and so["next_id"] == sg["next_id"]

@@ -252,3 +252,37 @@ def test_reduced_precision_at_thread_rupture_horizon():
         assert len(b["id"]) == len(ref["id"]) >= 2
         assert np.allclose(np.sort(b["volume"]), np.sort(ref["volume"]), rtol=1e-3)
         assert drift <= 1e-6
+
+
+def test_fp32_step_with_walls_matches_oracle():
+    """One FP32 step of a walled scene (gravity, TRT, blobs away from and
+    next to the walls) from the state the GPU reached, run by the oracle
+    from that same state: cell types, bubble IDs and the bubble table
+    exact, the fields within FP32 rounding.  Covers the FP32 geometry that
+    reads plain fill-level rows in the interior and mirrors samples at the
+    walls."""
+    import oracle
+    from paper_1604_01632_amd import Domain
+    from tests.parity import compare_fp32_step, near_tie, oracle_from_state
+    oracle.build(force=False)
+    sc = scenes.merge_ids_if_touching(scenes.random_blobs(
+        n=(26, 22, 20), nblob=5, seed=21, walls=True, g=(0.0, 0.0, -2e-4), rmin=3.0, rmax=5.0))
+    params = sc.params(collision=1)
+    g = Domain.from_scene(sc, "fp32", collision=1)
+    g.step(25)
+    before = g.read()
+    bb, sb = g.bubbles(), before["scalars"]
+    o = oracle_from_state(params, before, bb, sb)
+    t_before = before["cell_type"].copy()
+    _, normal = o.geometry()
+    c = oracle.lattice()[0]
+
+    def audit(i):
+        return near_tie(i, t_before, normal, c, (sc.nz, sc.ny, sc.nx))
+    audit.t_before = t_before
+    o.step(1)
+    g.step(1)
+    dg = g.read()
+    compare_fp32_step(o.read(), o.bubbles(), o.scalars(), dg, g.bubbles(), dg["scalars"],
+                      sc.nx * sc.ny * sc.nz, params.get("eps_convert", 1e-2), audit)
+    g.close()
