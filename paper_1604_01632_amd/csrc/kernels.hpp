@@ -1574,6 +1574,7 @@ __device__ __forceinline__ void bubble_volumes(const Dev &d, Blk bk) {
     const long long q = q0 + threadIdx.x;
     const long long s = q / SUB;
     const bool live = q < nq && d.b_live[s];
+    if (!__ballot(live)) continue;  // no live slot in this wave (uniform per wave)
     long long w[VACC];
 #pragma unroll
     for (int c = 0; c < VACC; ++c) w[c] = 0;
