@@ -70,6 +70,7 @@ def lib():
         L.orc_lattice.argtypes = [P, P, P]
         L.orc_feq.argtypes = [C.c_double, P, P]
         L.orc_collide.argtypes = [C.POINTER(_Params), P, P, P, P]
+        L.orc_boundary_velocity.argtypes = [C.POINTER(_Params), P, P]
         L.orc_geometry.argtypes = [P, P, P]
         L.orc_label.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P]
         L.orc_fsum.restype = C.c_double
@@ -127,6 +128,16 @@ def collide(params: dict, fin):
     u = np.zeros(3, np.float64)
     lib().orc_collide(C.byref(p), _ptr(fin), _ptr(fout), _ptr(rho), _ptr(u))
     return fout, float(rho[0]), u
+
+
+def boundary_velocity(params: dict, fs) -> np.ndarray:
+    """Velocity the interface reconstruction uses for a cell with
+    post-collision PDFs fs."""
+    p = make_params(params)
+    fs = np.ascontiguousarray(fs, dtype=np.float64)
+    u = np.zeros(3, np.float64)
+    lib().orc_boundary_velocity(C.byref(p), _ptr(fs), _ptr(u))
+    return u
 
 
 def fsum(values) -> float:

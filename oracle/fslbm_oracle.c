@@ -63,7 +63,9 @@ static int opposite(int a) {
  * of the terms rounded once to the nearest double, independent of order.
  * Shewchuk's method (1997): keep non-overlapping partials whose sum is
  * exact, updated with error-free two-sums; at the end add them from the
- * largest down and correct a half-way case so that ties round to even. */
+ * largest down and correct a half-way case so that ties round to even
+ * (the correction used by R. Hettinger's msum recipe, which is also the
+ * algorithm of Python's math.fsum). */
 typedef struct {
   double *p;
   int n, cap;
@@ -259,6 +261,22 @@ void orc_collide(const orc_params *p, const double *fin, double *fout, double *r
   u_out[0] = u[0];
   u_out[1] = u[1];
   u_out[2] = u[2];
+}
+
+/* Velocity at the free boundary (Sec. 2.2: the gas-side equilibrium uses
+ * the current velocity at the boundary): the cell's own last collision
+ * velocity, recovered from its post-collision PDFs f*.  Under the Guo
+ * scheme the collision adds rho g to the momentum, sum c f* = rho u +
+ * rho g / 2 with u the collision velocity, so u = sum c f* / rho - g / 2. */
+void orc_boundary_velocity(const orc_params *p, const double *fs, double *ub) {
+  double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < Q; ++a) {
+    r += fs[a];
+    j[0] += CX[a] * fs[a];
+    j[1] += CY[a] * fs[a];
+    j[2] += CZ[a] * fs[a];
+  }
+  for (int k = 0; k < 3; ++k) ub[k] = j[k] / r - 0.5 * p->g[k];
 }
 
 /* ------------------------------------------------- normals and curvature -- */
@@ -652,17 +670,8 @@ static void phase_a_cell(orc *o, int64_t i, double bucket_share) {
     int32_t b = bubble_index(o, o->id[i]);
     double p_gas = o->b_p[b] + 2.0 * o->P.sigma * kappa; /* p_V + 2 sigma kappa */
     double rho_gas = 3.0 * p_gas;                        /* p = rho cs^2 */
-    /* velocity at the boundary: the cell's own last collision velocity,
-     * recovered from its post-collision PDFs */
-    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
-    for (int a = 0; a < Q; ++a) {
-      r += fs[a];
-      j[0] += CX[a] * fs[a];
-      j[1] += CY[a] * fs[a];
-      j[2] += CZ[a] * fs[a];
-    }
     double ub[3];
-    for (int k = 0; k < 3; ++k) ub[k] = j[k] / r - 0.5 * o->P.g[k];
+    orc_boundary_velocity(&o->P, fs, ub);
     orc_feq(rho_gas, ub, feq_gas);
   }
 

@@ -79,6 +79,9 @@ void orc_feq(double rho, const double *u, double *out /*19*/);
 /* One collision of fin (19 values) with the oracle's parameters; writes the
  * post-collision values and the collision density and velocity. */
 void orc_collide(const orc_params *p, const double *fin, double *fout, double *rho, double *u);
+/* Velocity of the free boundary used in the gas-side equilibrium of an
+ * interface cell, from its post-collision PDFs fs[19]. */
+void orc_boundary_velocity(const orc_params *p, const double *fs, double *u /*3*/);
 /* Normal (Youngs gradient) and curvature (height function) of every
  * interface cell of the current state; other cells get 0. */
 void orc_geometry(const orc *o, double *kappa /*N*/, double *normal /*3N*/);

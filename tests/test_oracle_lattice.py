@@ -130,3 +130,24 @@ def test_guo_force_momentum(oracle_lib):
         assert np.allclose(u, (c.T @ fin + 0.5 * rho * g) / rho, rtol=0, atol=1e-16)
         assert np.allclose(c.T @ fout, rho * u + 0.5 * rho * g, rtol=0, atol=2e-15)
         assert fout.sum() == pytest.approx(rho, rel=1e-15)
+
+
+@pytest.mark.parametrize("collision", [0, 1])
+@pytest.mark.parametrize("seed", range(3))
+def test_boundary_velocity_is_the_collision_velocity(oracle_lib, collision, seed):
+    """The gas-side equilibrium of an interface cell uses the velocity at
+    the boundary (Sec. 2.2), read as the cell's own last collision
+    velocity.  It is recovered from the post-collision PDFs, which under the
+    Guo scheme carry rho u + rho g / 2 of momentum: the recovered velocity
+    must equal the velocity the collision itself used, to round-off.  A
+    recovery without the -g/2 shift is off by g/2 (here >= 5e-5)."""
+    rng = np.random.default_rng(300 + seed)
+    fin = oracle_lib.feq(rng.uniform(0.97, 1.03), rng.uniform(-0.05, 0.05, 3))
+    fin = fin * rng.uniform(0.95, 1.05, 19)
+    g = tuple(rng.uniform(-2e-3, 2e-3, 3) + np.sign(rng.uniform(-1, 1, 3)) * 1e-4)
+    params = _params(collision=collision, tau=float(rng.uniform(0.55, 1.2)), g=g)
+    fout, rho, u = oracle_lib.collide(params, fin)
+    ub = oracle_lib.boundary_velocity(params, fout)
+    assert np.max(np.abs(ub - u)) <= 1e-15
+    # the shift matters at this size
+    assert np.min(np.abs(np.asarray(g))) / 2 > 4e-5

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import scenes
-from scenes import IFACE, LIQ
+from scenes import IFACE, LIQ, WALL
 
 P0 = scenes.P0
 
@@ -126,6 +126,71 @@ def test_laplace_jump(oracle_lib, R):
     assert np.mean(dp) / np.mean(lap) == pytest.approx(1.0, abs=0.1)
 
 
+def _laplace_ratio(oracle_lib, sc, R, c, steps=200, window=50):
+    """Mean of p_bubble - p_liquid over the last `window` of `steps` steps,
+    over 2 sigma / R_eff with R_eff = (3 V / 4 pi)^(1/3); the liquid
+    pressure rho / 3 is averaged over liquid cells at least R + 4 from the
+    centre."""
+    n = sc.nx
+    o = oracle_lib.Oracle.from_scene(sc)
+    idx = np.arange(sc.n)
+    r = np.sqrt((idx % n + 0.5 - c) ** 2 + ((idx // n) % n + 0.5 - c) ** 2
+                + (idx // (n * n) + 0.5 - c) ** 2)
+    o.step(steps - window)
+    dp, lap, nb = [], [], []
+    for s in range(window):
+        o.step(1)
+        d = o.read()
+        b = o.bubbles()
+        far = (d["cell_type"] == LIQ) & (r >= R + 4)
+        assert np.count_nonzero(far) > 100
+        dp.append(b["pressure"][0] - d["rho"][far].mean() / 3.0)
+        lap.append(2 * sc.sigma / (3 * b["volume"][0] / (4 * np.pi)) ** (1 / 3))
+        nb.append(len(b["id"]))
+    return float(np.mean(dp) / np.mean(lap)), float(np.mean(dp) * R / (2 * sc.sigma)), nb
+
+
+@pytest.mark.slow
+def test_laplace_jump_config1(oracle_lib):
+    """The static-bubble workload itself (32^3 periodic, R = 8, sigma =
+    1e-3, tau = 0.6, liquid at Laplace equilibrium with p0, 200 steps): the
+    bubble count stays 1 and the jump p_bubble - p_liquid over steps
+    151-200 is 2 sigma / R (Sec. 2.2, gas pressure p_V + 2 sigma kappa)
+    within 10 %.  A curvature of the wrong sign drives the jump to
+    -2 sigma / R, a missing factor 2 to sigma / R."""
+    oracle_lib.set_threads(8)
+    try:
+        ratio, scaled, nb = _laplace_ratio(oracle_lib, scenes.config("c1"), 8.0, 16.0)
+    finally:
+        oracle_lib.set_threads(1)
+    print(f"c1: dp / (2 sigma / R_eff) = {ratio:.4f}, dp R / (2 sigma) = {scaled:.4f}")
+    assert nb == [1] * len(nb)
+    assert ratio == pytest.approx(1.0, abs=0.1)
+    assert scaled == pytest.approx(1.0, abs=0.1)
+
+
+@pytest.mark.slow
+def test_laplace_jump_radius_sweep(oracle_lib):
+    """Bubbles of radius 6, 8 and 12 in a 48^3 box at the static-bubble
+    parameters (sigma = 1e-3, tau = 0.6, 200 steps): dp R / (2 sigma) is 1
+    within 10 % for each, so the jump scales as 1/R."""
+    oracle_lib.set_threads(8)
+    out = []
+    try:
+        for R in (6.0, 8.0, 12.0):
+            sc = scenes.spheres(n=(48, 48, 48), centers=((24.0, 24.0, 24.0),), radii=(R,),
+                                sigma=1e-3, tau=0.6)
+            ratio, scaled, nb = _laplace_ratio(oracle_lib, sc, R, 24.0)
+            assert nb == [1] * len(nb)
+            out.append(scaled)
+    finally:
+        oracle_lib.set_threads(1)
+    print("dp R / (2 sigma) for R = 6, 8, 12:", out)
+    for v in out:
+        assert v == pytest.approx(1.0, abs=0.1)
+    assert max(out) / min(out) < 1.1
+
+
 @pytest.mark.slow
 def test_compressed_bubble_ideal_gas(oracle_lib):
     """Two bubbles in a closed periodic box; bubble 0 starts with 20 % more
@@ -150,3 +215,98 @@ def test_compressed_bubble_ideal_gas(oracle_lib):
     R = (3 * b["volume"] / (4 * np.pi)) ** (1 / 3)
     pl = b["pressure"] - 2 * sigma / R
     assert abs(pl[0] - pl[1]) < 0.1 * abs(b0["pressure"][0] - b0["pressure"][1])
+
+
+def _hemisphere_pair(axis, side, n=24, M=14, R=7.0, drop=False):
+    """A sphere of radius R centred on a plane in a periodic box, and the
+    half of it on the liquid side of that plane put against a wall layer
+    (the wall plane lies half-way between the wall layer and the first
+    fluid layer).  Returns both scenes as (params, arrays) and the map from
+    the walled box's fluid cells to the free box's cells."""
+    # free box: n x n x 2M, sphere centre on the plane z = M (cell faces)
+    free = scenes.spheres(n=(n, n, 2 * M), centers=((n / 2.0, n / 2.0, float(M)),), radii=(R,),
+                          sigma=1e-3, rho_l=1.0)
+    if drop:
+        t = free.cell_type
+        free.phi = 1.0 - free.phi
+        free.cell_type = np.where(t == IFACE, IFACE, np.where(t == LIQ, scenes.GAS, LIQ)).astype(np.uint8)
+        free.bubble_id = np.where(free.cell_type == LIQ, -1, 0).astype(np.int32)
+    t3 = free.cell_type.reshape(2 * M, n, n)
+    p3 = free.phi.reshape(2 * M, n, n)
+    b3 = free.bubble_id.reshape(2 * M, n, n)
+    nzw = M + 2  # wall, M fluid layers, wall
+    tw = np.full((nzw, n, n), WALL, np.uint8)
+    pw = np.zeros((nzw, n, n))
+    bw = np.full((nzw, n, n), -1, np.int32)
+    if side == 0:
+        # hemisphere on the low wall: walled layer k (1..M) = free layer M - 1 + k
+        src = slice(M, 2 * M)
+    else:
+        # hemisphere on the high wall: walled layer k (1..M) = free layer k - 1
+        src = slice(0, M)
+    tw[1:M + 1], pw[1:M + 1], bw[1:M + 1] = t3[src], p3[src], b3[src]
+    fz = np.arange(M) + (M if side == 0 else 0)  # free layer of walled layer 1 + k
+    # the wall axis is z above; move it to `axis` (arrays are [z, y, x])
+    perm = {2: (0, 1, 2), 1: (1, 0, 2), 0: (2, 1, 0)}[axis]
+    tw, pw, bw = (np.transpose(a, perm).copy() for a in (tw, pw, bw))
+    tf, pf, bf = (np.transpose(a, perm).copy() for a in (t3, p3, b3))
+    per = [1, 1, 1]
+    per[axis] = 0
+
+    def make(t, p, b, periodic):
+        nz_, ny_, nx_ = t.shape
+        N = t.size
+        params = dict(nx=nx_, ny=ny_, nz=nz_, periodic=tuple(periodic), tau=0.6, sigma=1e-3,
+                      g=(0.0, 0.0, 0.0), collision=0, eps_convert=1e-2)
+        return (params, t.ravel(), p.ravel(), np.ones(N), np.zeros(3 * N), b.ravel(),
+                [(0, 0, -1.0, P0)])
+
+    return make(tw, pw, bw, per), make(tf, pf, bf, (1, 1, 1)), fz
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("side", [0, 1])
+@pytest.mark.parametrize("drop", [False, True])
+def test_wall_mirror_hemisphere_equals_half_sphere(oracle_lib, axis, side, drop):
+    """Fill levels beyond a wall are the mirror image across the wall plane
+    (a 90 degree contact angle; the paper leaves the geometry at walls
+    open).  Then a hemisphere sitting on a wall sees exactly the fill levels
+    of the full sphere in free space, so every interface cell of the walled
+    box has the normal and curvature of the corresponding free-space cell,
+    on either wall of every axis.  A mirror one layer off (about the wall
+    layer's centre, or about the far side of the first fluid layer) fails."""
+    walled, free, fz = _hemisphere_pair(axis, side, drop=drop)
+    ow = oracle_lib.Oracle(*walled)
+    of = oracle_lib.Oracle(*free)
+    kw, nw = ow.geometry()
+    kf, nf = of.geometry()
+    pw, pf = walled[0], free[0]
+    shape_w = (pw["nz"], pw["ny"], pw["nx"])
+    shape_f = (pf["nz"], pf["ny"], pf["nx"])
+    kw3, kf3 = kw.reshape(shape_w), kf.reshape(shape_f)
+    nw3 = nw.reshape((3,) + shape_w)
+    nf3 = nf.reshape((3,) + shape_f)
+    ax3 = 2 - axis  # array axis of the wall axis
+    sel_w = [slice(None)] * 3
+    sel_f = [slice(None)] * 3
+    sel_w[ax3] = slice(1, len(fz) + 1)
+    sel_f[ax3] = fz
+    sel_w, sel_f = tuple(sel_w), tuple(sel_f)
+    tw = walled[1].reshape(shape_w)[sel_w]
+    iface = tw == IFACE
+    assert np.count_nonzero(iface) > 50
+    # next to the wall there are interface cells, whose stencils reach
+    # beyond it
+    first = [slice(None)] * 3
+    first[ax3] = 0 if side == 0 else -1
+    assert np.count_nonzero(tw[tuple(first)] == IFACE) > 8
+    assert np.array_equal(tw, free[1].reshape(shape_f)[sel_f])
+    dk = np.abs(kw3[sel_w] - kf3[sel_f])[iface]
+    assert np.max(dk) <= 1e-13
+    for c in range(3):
+        dn = np.abs(nw3[c][sel_w] - nf3[c][sel_f])[iface]
+        assert np.max(dn) <= 1e-13
+    # the curvature is that of a sphere, not of a flattened cap
+    ph = walled[2].reshape(shape_w)[sel_w]
+    mid = iface & (ph > 0.05) & (ph < 0.95)
+    assert abs(np.mean(kw3[sel_w][mid]) * 7.0) == pytest.approx(1.0, abs=0.05)
