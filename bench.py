@@ -3,14 +3,18 @@
 Default workload: 256^3 periodic box with 16 gas threads (radius 8, 0.1 R
 sinusoidal radius perturbation of wavelength 72, 1e-3 fill-level noise),
 tau = 0.55, sigma = 5e-3, FP32 storage and arithmetic.  The threads
-rupture (Rayleigh-Plateau) between steps ~1000 and ~1500 into about three
-bubbles each; the default window (1000 warm-up steps, 1000 timed steps)
-therefore contains the bubble splits and their labelling runs.
+rupture (Rayleigh-Plateau) between steps 1128 and 1192 into about three
+bubbles each.  The benchmark first evolves the scene to step 1120, then
+runs the warm-up and the timed window (default 5 + 80 steps), so that the
+window holds the bubble splits and their labelling runs whatever the
+warm-up and window lengths.
 
 Prints one JSON line (rank 0, N = 1) with the whole-step throughput in
 MLUPS, the HBM roofline of the dominant kernel (liquid-cell stream-collide)
-measured with HIP events on the library's stream, and the CPU oracle timed
-on a bounded sample of the same workload.
+measured with HIP events on the library's stream over the timed window,
+the achievable bandwidth of a plain streaming copy, and the CPU oracle
+timed on a bounded sample of the same workload (all host threads of this
+job and one thread).
 """
 from __future__ import annotations
 
@@ -26,6 +30,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+# The 16 threads of the 256^3 workload rupture between steps 1128 and 1192
+# (51 bubble merges and splits, FP32); starting the warm-up at step 1120
+# puts them in the timed window.
+RUPTURE_START = 1120
 METRIC = "FSLBM MLUPS and % of HBM roofline; served p50/p99 latency vs plain"
 
 
@@ -53,12 +61,33 @@ def count_types(t) -> dict:
     return dict(gas=int(b[0]), iface=int(b[1]), liq=int(b[2]), other=int(b[0] + b[3] + b[4]))
 
 
-def cpu_baseline(scene, seconds: float, threads: int) -> dict:
-    """The oracle as it stands, on the host cores, on whole steps of the same
-    workload until about `seconds` of CPU time have passed."""
+def host_threads() -> int:
+    """Host threads this job may use: the OpenMP setting of the host (the
+    GPU machine gives each GPU a share of its cores), else the CPUs of this
+    process's affinity mask."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(scene, seconds: float, threads: int, max_steps: int):
     import oracle
 
-    oracle.build(force=False)
     oracle.set_threads(threads)
     o = oracle.Oracle.from_scene(scene)
     steps, t0 = 0, time.perf_counter()
@@ -66,12 +95,49 @@ def cpu_baseline(scene, seconds: float, threads: int) -> dict:
         o.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= seconds or steps >= 50:
+        if el >= seconds or steps >= max_steps:
             break
-    mlups = scene.n * steps / el / 1e6
-    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{scene.name} {scene.nx}x{scene.ny}x{scene.nz}, FP64 oracle, first {steps} "
-                      f"step(s) from the initial state, {el:.1f} s wall"}
+    del o
+    return scene.n * steps / el / 1e6, steps, el
+
+
+def cpu_baseline(scene, seconds: float, threads: int, single: bool) -> dict:
+    """The oracle as it stands, on the host cores, on whole steps of the same
+    workload from its initial state until about `seconds` have passed:
+    once with `threads` OpenMP threads and, if `single`, once with one
+    thread (at least one whole step)."""
+    import oracle
+
+    oracle.build(force=False)
+    mlups, steps, el = _oracle_rate(scene, seconds, threads, 50)
+    out = {"value": round(mlups, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{scene.name} {scene.nx}x{scene.ny}x{scene.nz}, FP64 oracle, first {steps} "
+                     f"step(s) from the initial state, {el:.1f} s wall on {threads} threads",
+           "cpu_model": cpu_model()}
+    if single:
+        m1, s1, e1 = _oracle_rate(scene, 1.0, 1, 1)
+        out["single_thread"] = {"value": round(m1, 4), "unit": "MLUPS", "cores": 1,
+                                "sample": f"first {s1} step(s), {e1:.1f} s wall"}
+    oracle.set_threads(1)
+    return out
+
+
+def copy_bandwidth_context(mib: int = 1024, reps: int = 10) -> dict:
+    """Achievable HBM bandwidth: the library's streaming copy kernel over
+    two buffers of `mib` MiB."""
+    import torch
+
+    import paper_1604_01632_amd as F
+
+    n = mib * (1 << 20)
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    gbs = F.fslbm_copy_bandwidth(dst, src, reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "kernel": "fslbm_copy_bandwidth (16-byte non-temporal loads and stores)",
+            "bytes_each_way": n, "reps": reps}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_p1_256cubed_fp32_hbm_traffic.md")
@@ -347,20 +413,25 @@ def bench_served(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=80)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--start-step", type=int, default=-1,
+                    help="steps run before the warm-up (default: the rupture epoch of p1, "
+                         f"step {RUPTURE_START}; 0 for other workloads)")
     ap.add_argument("--workload", default="p1",
                     help="p1 (default: 256^3 thread rupture), c1/c2/c3, batched, served, forms")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16dev"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--phase-period", type=int, default=25,
-                    help="bracket every N-th timed step with per-phase HIP events (the "
-                         "kernel time of the roofline figure); each event delays the next "
-                         "kernel by a few microseconds, so sampling keeps the window close "
-                         "to an untimed one")
+    ap.add_argument("--no-single-thread", action="store_true",
+                    help="skip the single-threaded oracle sample")
     ap.add_argument("--no-phase-timing", action="store_true",
-                    help="time the window without per-phase events (no roofline figure)")
+                    help="time the window without events around the stream-collide kernel "
+                         "(no roofline figure)")
+    ap.add_argument("--no-phase-breakdown", dest="phase_breakdown", action="store_false",
+                    help="skip the rerun of the window with every phase timed")
+    ap.add_argument("--no-copy-probe", action="store_true",
+                    help="skip the achievable-bandwidth copy probe")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter scaling) and exit")
     ap.add_argument("--domains", type=int, default=256, help="batched workload: domains")
@@ -396,50 +467,84 @@ def main() -> int:
     sc = scenes.config(args.workload)
     prec = F.PRECISIONS[args.precision]
     store_bytes = {0: 8, 1: 4, 2: 2}[prec]
-    dom = F.Domain.from_scene(sc, args.precision)
+    start = args.start_step if args.start_step >= 0 else (RUPTURE_START if args.workload == "p1" else 0)
     N = sc.n
-    log(f"[bench] {sc.name}: {sc.nx}x{sc.ny}x{sc.nz} ({N} cells) {args.precision}; "
-        f"warmup {args.warmup} steps")
-    dom.step(args.warmup)
-    torch.cuda.synchronize()
-    r0 = dom.read(("cell_type",))
-    c0 = count_types(r0["cell_type"])
-    s0 = r0["scalars"]
-    b0 = dom.bubbles()
 
-    period = 0 if args.no_phase_timing else max(1, args.phase_period)
-    F.fslbm_set_timing(dom.handle, period)
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    dom.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    T = F.fslbm_get_timing(dom.handle)
-    F.fslbm_set_timing(dom.handle, 0)
+    def run_window(phases, period):
+        """Evolve a fresh domain to `start`, warm up, then time the window;
+        returns the measurements and the domain."""
+        dom = F.Domain.from_scene(sc, args.precision)
+        if start:
+            dom.step(start)
+        dom.step(args.warmup)
+        torch.cuda.synchronize()
+        r0 = dom.read(("cell_type",))
+        b0 = dom.bubbles()
+        F.fslbm_set_timing(dom.handle, period, phases)
+        stream = torch.cuda.current_stream()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        dom.step(args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        T = F.fslbm_get_timing(dom.handle)
+        F.fslbm_set_timing(dom.handle, 0)
+        r1 = dom.read(("cell_type",))
+        return dict(gpu_ms=ev0.elapsed_time(ev1), wall=wall, T=T, r0=r0, r1=r1, b0=b0,
+                    b1=dom.bubbles()), dom
 
-    r1 = dom.read(("cell_type",))
-    c1 = count_types(r1["cell_type"])
-    s1 = r1["scalars"]
-    b1 = dom.bubbles()
-    ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
+    log(f"[bench] {sc.name}: {sc.nx}x{sc.ny}x{sc.nz} ({N} cells) {args.precision}; evolve to step "
+        f"{start}, warm-up {args.warmup}, timed {args.steps}")
+    # the timed window: events only around the stream-collide kernel, on
+    # about ten of its steps (each event pair delays the stream by ~10 us)
+    period = 0 if args.no_phase_timing else max(1, args.steps // 10)
+    m, dom = run_window(["bulk"], period)
+    dom.close()
+    del dom
+    torch.cuda.empty_cache()
+    T = m["T"]
+    c0, c1 = count_types(m["r0"]["cell_type"]), count_types(m["r1"]["cell_type"])
+    s0, s1 = m["r0"]["scalars"], m["r1"]["scalars"]
+    ms_per_step = max(m["gpu_ms"], m["wall"] * 1e3) / args.steps
     mlups = N / (ms_per_step * 1e-3) / 1e6
     counts = {k: 0.5 * (c0[k] + c1[k]) for k in c0}
     bytes_bulk = bulk_bytes_per_launch(counts, store_bytes)
     bulk_avg_ms = T["bulk_ms"] / max(1, T["steps"])
     achieved = bytes_bulk / (bulk_avg_ms * 1e-3) / 1e9 if T["steps"] else 0.0
-    phases = {k: round(T[k] / max(1, T["steps"]) * 1e3, 2) for k in
-              ("bulk_ms", "iface_ms", "convert_ms", "excess_ms", "gather_ms", "label_ms",
-               "bubbles_ms")}
-    log(f"[bench] per-step phase times (us): {phases}")
-    log(f"[bench] window: topology changes {s1['n_topology'] - s0['n_topology']}, bubbles "
-        f"{len(b0['id'])} -> {len(b1['id'])}, mass drift "
+    topo = int(s1["n_topology"] - s0["n_topology"])
+    # whole-step algorithmic traffic: fluid cells move B bytes (PDFs read and
+    # written, flags, fill level, mass and bubble IDs of the thin interface
+    # layer amortised), gas, wall and inlet cells their flag byte
+    b_alg = 2 * 19 * store_bytes + 8
+    n_fluid = counts["liq"] + counts["iface"]
+    whole_gbs = (n_fluid * b_alg + (N - n_fluid) * 1) / (ms_per_step * 1e-3) / 1e9
+    log(f"[bench] window: {ms_per_step:.4f} ms/step, {mlups:.1f} MLUPS, topology changes {topo}, "
+        f"bubbles {len(m['b0']['id'])} -> {len(m['b1']['id'])}, mass drift "
         f"{abs(s1['total_mass'] - s0['total_mass']) / s0['total_mass']:.2e}, cells {c1}")
+    if topo == 0:
+        log("[bench] WARNING: no bubble merge or split in the timed window: this is not the "
+            "breakup-active case")
+    phases = None
+    if args.phase_breakdown:
+        # the same window again (the run is deterministic), every phase timed
+        # on every step: where the time of a step goes
+        mp, dom = run_window(None, 1)
+        dom.close()
+        del dom
+        torch.cuda.empty_cache()
+        phases = {k: round(mp["T"][k] / max(1, mp["T"]["steps"]) * 1e3, 2) for k in
+                  ("bulk_ms", "iface_ms", "convert_ms", "excess_ms", "gather_ms", "label_ms",
+                   "bubbles_ms")}
+        log(f"[bench] per-step phase times (us, same window rerun, every phase timed): {phases}")
+    copy = copy_bandwidth_context() if not args.no_copy_probe else None
+    if copy:
+        log(f"[bench] streaming copy: {copy['GBs']} GB/s ({copy['frac_of_peak']} of peak)")
+    desc = {"p1": "16 gas threads R=8 (0.1R sinusoidal perturbation, wavelength 72, 1e-3 noise), "
+                  "tau=0.55, sigma=0.005"}.get(args.workload, f"tau={sc.tau}, sigma={sc.sigma}")
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -454,17 +559,22 @@ def main() -> int:
         "dtype": {"fp64": "f64", "fp32": "f32", "fp16dev": "f16-storage/f32"}[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": f"{sc.name}: {sc.nx}x{sc.ny}x{sc.nz} periodic D3Q19 FSLBM + bubble model, "
-                        "16 gas threads R=8 (0.1R sinusoidal perturbation, wavelength 72, 1e-3 "
-                        f"noise), tau={sc.tau}, sigma={sc.sigma}, {args.precision}, timed after "
-                        f"{args.warmup} warm-up steps",
+            "workload": f"{sc.name}: {sc.nx}x{sc.ny}x{sc.nz} "
+                        f"{'periodic' if all(sc.periodic) else 'walled'} D3Q19 FSLBM + bubble "
+                        f"model, {desc}, {args.precision}; window = steps "
+                        f"{start + args.warmup + 1}..{start + args.warmup + args.steps}",
             "cells": N,
             "precision": args.precision,
-            "topology_changes_in_window": int(s1["n_topology"] - s0["n_topology"]),
-            "bubbles_start_end": [int(len(b0["id"])), int(len(b1["id"]))],
-            "whole_step_alg_GBs": round(N * (2 * 19 * store_bytes + 8) / (ms_per_step * 1e-3) / 1e9, 1),
+            "start_step": start,
+            "topology_changes_in_window": topo,
+            "breakup_active": topo > 0,
+            "bubbles_start_end": [int(len(m["b0"]["id"])), int(len(m["b1"]["id"]))],
+            "whole_step_alg_GBs": round(whole_gbs, 1),
+            "whole_step_frac": round(whole_gbs / HBM_PEAK_GBS, 4),
+            "whole_step_bytes_per_fluid_cell": b_alg,
+            "bulk_sampled_steps": int(T["steps"]),
             "phase_us": phases,
-            "phase_sampled_steps": int(T["steps"]),
+            "achievable_copy": copy,
         },
         "roofline": {
             "kernel": "k_bulk (liquid-cell stream-collide)",
@@ -478,13 +588,11 @@ def main() -> int:
             "avg_launch_us": round(bulk_avg_ms * 1e3, 2),
         },
     }
-    dom.close()
-    del dom
-    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        log(f"[bench] cpu baseline: oracle on {threads} threads, ~{args.cpu_seconds} s")
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds, threads)
+        threads = host_threads()
+        log(f"[bench] cpu baseline: oracle on {threads} threads (~{args.cpu_seconds} s), then on "
+            "one thread (one step)")
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds, threads, not args.no_single_thread)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -38,8 +38,8 @@
  *   handles are independent.
  *   Errors: every call returns FSLBM_OK (0) or a negative status;
  *   fslbm_last_error() returns the calling thread's message for the last
- *   failure.  Device-side failures (bubble table full, non-finite mass) are
- *   reported by the next synchronising call.
+ *   failure.  Device-side failures (bubble table full, non-finite values,
+ *   a failed watchdog check) are reported by the next synchronising call.
  */
 #ifndef FSLBM_H
 #define FSLBM_H
@@ -56,7 +56,9 @@ enum {
   FSLBM_EINVAL = -1,    /* invalid argument or input state */
   FSLBM_ENOMEM = -2,    /* workspace too small */
   FSLBM_EDEVICE = -3,   /* HIP runtime error */
-  FSLBM_ENUMERIC = -4,  /* non-finite total mass detected */
+  FSLBM_ENUMERIC = -4,  /* non-finite density, mass or fill level; a broken
+                           interface layer or mass drift found by the
+                           watchdog; an internal list overflow */
   FSLBM_ECAPACITY = -5  /* bubble table full */
 };
 
@@ -91,7 +93,30 @@ typedef struct {
   double inject_rate;   /* V* added per step to each bubble owning INLET cells */
   int32_t max_bubbles;  /* capacity of the device bubble table (>= 1) */
   int32_t force_topology; /* 1: label the gas region every step (testing) */
+  int32_t freeze_conversions; /* 1: no interface cell is filled or emptied,
+                                 so cell types and bubbles stay fixed
+                                 (testing the flow and the interface update
+                                 on a fixed geometry) */
+  int32_t watchdog_every; /* K > 0: after every K-th step (counted from step
+                             0 of the run) a device check runs, and
+                             fslbm_step waits for it and returns
+                             FSLBM_ENUMERIC if it failed: a liquid cell next
+                             to a gas or inlet cell (the interface must stay
+                             a closed layer, Sec. 2.2), a gas-region cell
+                             without a live bubble, or a relative drift of
+                             the total mass beyond watchdog_drift.  0: off */
+  double watchdog_drift;  /* relative total-mass drift (against the mass at
+                             creation) tolerated by the watchdog; <= 0: not
+                             checked */
+  int32_t debug_flags;    /* FSLBM_DEBUG_* bits (testing only) */
+  int32_t pad_;
 } fslbm_params;
+
+/* debug_flags: accept a liquid cell next to a gas or inlet cell at
+ * creation (for tests of the watchdog; the step is not defined on such a
+ * state, but every kernel still reads and writes only inside the
+ * workspace). */
+enum { FSLBM_DEBUG_NO_LAYER_CHECK = 1 };
 
 /* Initial bubble: v_star > 0 gives V* directly (restart); otherwise
  * V* = V(0) p_init / p0, with V(0) the volume of the initial state. */
@@ -119,7 +144,7 @@ typedef struct {
                           over all interface cells in the next step */
   double total_mass;   /* sum over liquid rho + interface m + bucket, FP64,
                           of the last step */
-  int64_t n_topology;  /* steps in which labelling ran */
+  int64_t n_topology;  /* steps in which a merge or split created bubbles */
 } fslbm_scalars;
 
 /* Exact device workspace size for these parameters (0 on invalid params). */
@@ -150,18 +175,31 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
                  const double *mass_init, const fslbm_scalars *restore, void *device_workspace,
                  size_t workspace_bytes, void *stream, void **out_handle);
 
-/* Enqueue n_steps >= 0 time steps on the handle's stream. */
+/* Enqueue n_steps >= 0 time steps on the handle's stream.  One step is the
+ * update of Sec. 2: stream and collide (Sec. 2.1), the free-surface
+ * boundary condition, mass exchange and cell conversion (Sec. 2.2), bubble
+ * volumes and pressures (Sec. 2.2, ideal-gas equation) and the merge and
+ * split rules (Sec. 2.3.1, 2.3.2).  Returns after enqueueing, except when
+ * the watchdog is due (watchdog_every): then it waits for the check and
+ * returns FSLBM_ENUMERIC (after the failing step; later steps are not
+ * enqueued) if it failed. */
 int fslbm_step(void *handle, int32_t n_steps);
 
-/* Synchronise and copy state to the host; any pointer may be NULL.
+/* Synchronise and copy state to the host; any pointer may be NULL.  The
+ * state is that of Sec. 2.2: cell types, fill levels phi = m / rho, masses
+ * and the PDFs of interface and liquid cells, plus the bubble ID of every
+ * gas-region cell (Sec. 2.3).
  * f[19N] is the post-collision PDF set (undefined on GAS / WALL / INLET
  * cells), mass is m on interface cells and rho on liquid cells, rho and u
- * are recovered from f (u = sum c f / rho - g / 2). */
+ * are recovered from f (u = sum c f / rho - g / 2).  Returns the first
+ * asynchronous error of past steps (ECAPACITY, ENUMERIC) instead, if any. */
 int fslbm_read_fields(void *handle, uint8_t *cell_type, double *phi, double *mass, double *f,
                       int32_t *bubble_id, double *rho, double *u, fslbm_scalars *scalars);
 
 /* Synchronise and copy the live bubbles, sorted by ID, into out[capacity];
- * *n_out receives the number of live bubbles (ECAPACITY if > capacity). */
+ * *n_out receives the number of live bubbles (ECAPACITY if > capacity).
+ * A bubble is the data set {ID, V*, V} of Sec. 2.2 and 2.3 with the
+ * pressure of the ideal-gas equation (Sec. 2.2), p = p0 V* / max(V, 1e-2). */
 int fslbm_bubbles(void *handle, fslbm_bubble *out, int32_t capacity, int32_t *n_out);
 
 /* Synchronise and report device-side failures of past steps. */
@@ -180,15 +218,32 @@ typedef struct {
   int64_t steps;    /* sampled (timed) steps */
 } fslbm_timing;
 
+/* Phases of a step, as bits of the timing mask. */
+enum {
+  FSLBM_PHASE_IFACE = 1, FSLBM_PHASE_BULK = 2, FSLBM_PHASE_CONVERT = 4, FSLBM_PHASE_EXCESS = 8,
+  FSLBM_PHASE_GATHER = 16, FSLBM_PHASE_LABEL = 32, FSLBM_PHASE_BUBBLES = 64, FSLBM_PHASE_ALL = 127
+};
+
 /* Event timing of every period-th step enqueued from now on (the first of
- * them included); period 1 times every step, 0 disables timing.  Each event
- * delays the next kernel by a few microseconds, so a period well above 1
- * keeps the timed stream close to an untimed one.  Waits for the handle's
- * stream and clears the accumulated times.  FSLBM_EINVAL for period < 0. */
-int fslbm_set_timing(void *handle, int32_t period);
+ * them included); period 1 times every step, 0 disables timing.  Only the
+ * phases in phase_mask (FSLBM_PHASE_* bits; 0 means all) are bracketed by
+ * events, the others report 0.  Each event delays the next kernel by a few
+ * microseconds, so a period well above 1 and a narrow mask keep the timed
+ * stream close to an untimed one.  Waits for the handle's stream and clears
+ * the accumulated times.  FSLBM_EINVAL for period < 0. */
+int fslbm_set_timing(void *handle, int32_t period, uint32_t phase_mask);
 
 /* Synchronise, report the accumulated times and clear them. */
 int fslbm_get_timing(void *handle, fslbm_timing *out);
+
+/* Diagnostics: achievable HBM bandwidth on this device.  Copies `bytes`
+ * (a multiple of 16) from src to dst, both device buffers owned by the
+ * caller and 16-byte aligned, reps times with a plain streaming copy kernel
+ * (16-byte non-temporal loads and stores) on `stream`, and writes to
+ * *gbs_out the bytes read plus written per second, averaged over the reps
+ * (HIP events).  EINVAL on bad arguments, EDEVICE on HIP errors. */
+int fslbm_copy_bandwidth(void *dst, const void *src, size_t bytes, int32_t reps, void *stream,
+                         double *gbs_out);
 
 /* Destroy the handle (no device memory is freed: it belongs to the caller). */
 int fslbm_destroy(void *handle);

@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
 
 class _Params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
-                ("periodic", C.c_int32 * 3), ("collision", C.c_int32), ("pad", C.c_int32),
+                ("periodic", C.c_int32 * 3), ("collision", C.c_int32), ("freeze_conversions", C.c_int32),
                 ("tau", C.c_double), ("trt_lambda", C.c_double), ("sigma", C.c_double),
                 ("g", C.c_double * 3), ("p0", C.c_double), ("eps", C.c_double),
                 ("inject_rate", C.c_double)]
@@ -92,6 +92,7 @@ def make_params(d: dict) -> _Params:
         p.periodic[k] = int(d["periodic"][k])
         p.g[k] = float(d["g"][k])
     p.collision = int(d.get("collision", 0))
+    p.freeze_conversions = int(d.get("freeze_conversions", 0))
     p.tau = float(d["tau"])
     p.trt_lambda = float(d.get("trt_lambda", 3.0 / 16.0))
     p.sigma = float(d["sigma"])

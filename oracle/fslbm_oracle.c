@@ -932,6 +932,7 @@ static int one_step(orc *o) {
     int no_liq = !any_neighbour_type(o, i, ORC_L);
     o->filled[i] = (uint8_t)(!near_in && (o->phi2[i] > 1.0 + eps || no_gas));
     o->emptied0[i] = (uint8_t)(o->phi2[i] < -eps || no_liq);
+    if (o->P.freeze_conversions) o->filled[i] = o->emptied0[i] = 0; /* fixed geometry */
   }
   for (int64_t i = 0; i < N; ++i)
     o->emptied[i] = (uint8_t)(o->emptied0[i] && !o->filled[i] &&

@@ -24,7 +24,7 @@ typedef struct {
   int32_t nx, ny, nz;
   int32_t periodic[3];
   int32_t collision;   /* 0: BGK (Sec. 2.1), 1: TRT (optional reading) */
-  int32_t pad;
+  int32_t freeze_conversions; /* 1: no interface cell is filled or emptied */
   double tau;          /* omega = 1 / tau */
   double trt_lambda;   /* TRT magic parameter */
   double sigma;        /* surface tension (Sec. 2.2, Laplace pressure) */

@@ -17,6 +17,9 @@ LIB_PATH = os.path.join(HERE, "libfslbm.so")
 
 FSLBM_OK, FSLBM_EINVAL, FSLBM_ENOMEM, FSLBM_EDEVICE, FSLBM_ENUMERIC, FSLBM_ECAPACITY = 0, -1, -2, -3, -4, -5
 FP64, FP32, FP16DEV = 0, 1, 2
+DEBUG_NO_LAYER_CHECK = 1
+PHASES = ("iface", "bulk", "convert", "excess", "gather", "label", "bubbles")
+PHASE_BITS = {name: 1 << k for k, name in enumerate(PHASES)}
 BGK, TRT = 0, 1
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16dev": FP16DEV}
 
@@ -33,7 +36,9 @@ class Params(C.Structure):
                 ("tau", C.c_double), ("trt_lambda", C.c_double), ("sigma", C.c_double),
                 ("g", C.c_double * 3), ("p0", C.c_double), ("eps_convert", C.c_double),
                 ("inject_rate", C.c_double), ("max_bubbles", C.c_int32),
-                ("force_topology", C.c_int32)]
+                ("force_topology", C.c_int32), ("freeze_conversions", C.c_int32),
+                ("watchdog_every", C.c_int32), ("watchdog_drift", C.c_double),
+                ("debug_flags", C.c_int32), ("pad_", C.c_int32)]
 
 
 class BubbleInit(C.Structure):
@@ -92,7 +97,9 @@ def lib() -> C.CDLL:
         L.fslbm_destroy.restype = C.c_int
         L.fslbm_destroy.argtypes = [P]
         L.fslbm_set_timing.restype = C.c_int
-        L.fslbm_set_timing.argtypes = [P, C.c_int32]
+        L.fslbm_set_timing.argtypes = [P, C.c_int32, C.c_uint32]
+        L.fslbm_copy_bandwidth.restype = C.c_int
+        L.fslbm_copy_bandwidth.argtypes = [P, P, C.c_size_t, C.c_int32, P, C.POINTER(C.c_double)]
         L.fslbm_get_timing.restype = C.c_int
         L.fslbm_get_timing.argtypes = [P, C.POINTER(Timing)]
         L.fslbm_last_error.restype = C.c_char_p
@@ -138,6 +145,10 @@ def make_params(d: dict) -> Params:
     p.inject_rate = float(d.get("inject_rate", 0.0))
     p.max_bubbles = int(d.get("max_bubbles", 1024))
     p.force_topology = int(d.get("force_topology", 0))
+    p.freeze_conversions = int(d.get("freeze_conversions", 0))
+    p.watchdog_every = int(d.get("watchdog_every", 0))
+    p.watchdog_drift = float(d.get("watchdog_drift", 0.0))
+    p.debug_flags = int(d.get("debug_flags", 0))
     return p
 
 
@@ -221,9 +232,25 @@ def fslbm_destroy(handle) -> None:
     _check(lib().fslbm_destroy(handle))
 
 
-def fslbm_set_timing(handle, period: int) -> None:
-    """Event timing of every `period`-th step (1: every step, 0: off)."""
-    _check(lib().fslbm_set_timing(handle, int(period)))
+def fslbm_set_timing(handle, period: int, phases=None) -> None:
+    """Event timing of every `period`-th step (1: every step, 0: off) for
+    the named phases (default: all)."""
+    mask = 0 if phases is None else sum(PHASE_BITS[p] for p in phases)
+    _check(lib().fslbm_set_timing(handle, int(period), mask))
+
+
+def fslbm_copy_bandwidth(dst, src, reps: int = 10, stream=None) -> float:
+    """GB/s (read + written) of the library's streaming copy kernel between
+    two CUDA tensors of equal byte size."""
+    import torch
+
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    out = C.c_double()
+    _check(lib().fslbm_copy_bandwidth(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
+                                      nbytes, int(reps), C.c_void_p(st.cuda_stream), C.byref(out)))
+    return out.value
 
 
 def fslbm_get_timing(handle) -> dict:

@@ -107,18 +107,28 @@ const char *check_params(const fslbm_params *p) {
   if (p->max_bubbles < 1 || p->max_bubbles > (1 << 20)) return "max_bubbles out of range";
   if (!(p->eps_convert >= 0.0)) return "eps_convert must be >= 0";
   if (!(p->p0 > 0.0)) return "p0 must be > 0";
+  if (p->force_topology != 0 && p->force_topology != 1) return "force_topology must be 0 or 1";
+  if (p->freeze_conversions != 0 && p->freeze_conversions != 1)
+    return "freeze_conversions must be 0 or 1";
+  if (p->watchdog_every < 0) return "watchdog_every must be >= 0";
+  if (p->debug_flags & ~FSLBM_DEBUG_NO_LAYER_CHECK) return "unknown debug_flags bits";
   return nullptr;
 }
 
 // --------------------------------------------------------------- context
 
 struct Ctx {
-  // per-phase event timing (fslbm_set_timing): every timing_period-th
-  // step enqueued since it was set is bracketed by events
+  // per-phase event timing (fslbm_set_timing): on every timing_period-th
+  // step enqueued since it was set, each phase in timing_mask is bracketed
+  // by a pair of events
   int timing_period = 0;
+  unsigned timing_mask = 0;
   long long timing_count = 0;
-  std::vector<hipEvent_t> events;  // PH_COUNT + 1 per timed step
-  size_t used = 0;
+  long long timed_steps = 0;
+  std::vector<hipEvent_t> events;  // two per timed phase
+  std::vector<int> event_phase;    // the phase of each pair
+  size_t used = 0;                 // pairs in use
+  long long host_step = 0;         // steps enqueued since step 0 of the run
   fslbm_params P;
   Launchers L;
   LaunchCfg cfg;
@@ -146,6 +156,8 @@ void build_devs(Ctx &c) {
   d.has_walls = !(d.per[0] && d.per[1] && d.per[2]);
   d.max_bubbles = c.P.max_bubbles;
   d.force_topology = c.P.force_topology;
+  d.freeze = c.P.freeze_conversions;
+  d.drift_tol = c.P.watchdog_drift;
   d.collision = c.P.collision;
   d.N = c.N;
   d.omega_p = 1.0 / c.P.tau;
@@ -414,9 +426,38 @@ int sync_and_check(Ctx &c) {
   Scalars sc;
   HIP_TRY(hipMemcpy(&sc, c.dev[0].sc, sizeof sc, hipMemcpyDeviceToHost));
   if (sc.err & ERR_CAPACITY) return fail(FSLBM_ECAPACITY, "bubble table full (max_bubbles)");
-  if (sc.err & ERR_NONFINITE) return fail(FSLBM_ENUMERIC, "non-finite total mass");
+  if (sc.err & ERR_NONFINITE)
+    return fail(FSLBM_ENUMERIC, "non-finite density, mass or fill level (or total mass)");
   if (sc.err & ERR_RANGE) return fail(FSLBM_ENUMERIC, "conversion candidate list overflow");
+  if (sc.err & ERR_LAYER)
+    return fail(FSLBM_ENUMERIC, "watchdog: a liquid cell touches a gas or inlet cell "
+                                "(the interface layer is not closed)");
+  if (sc.err & ERR_ORPHAN)
+    return fail(FSLBM_ENUMERIC, "watchdog: a gas-region cell has no live bubble");
+  if (sc.err & ERR_DRIFT) {
+    char m[160];
+    std::snprintf(m, sizeof m, "watchdog: total mass %.17g drifted from %.17g beyond %g relative",
+                  sc.total_mass, sc.mass_ref, c.P.watchdog_drift);
+    return fail(FSLBM_ENUMERIC, m);
+  }
   return FSLBM_OK;
+}
+
+bool watchdog_due(const Ctx &c) {
+  return c.P.watchdog_every > 0 && c.host_step % c.P.watchdog_every == 0;
+}
+
+// Achievable-bandwidth probe: a plain streaming copy with 16-byte
+// non-temporal loads and stores (each byte is read and written once).  It
+// gives the bandwidth a kernel that only streams can reach on the device,
+// as context for the roofline of the step kernels.
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_copy_stream(const v4u *__restrict__ src,
+                                                      v4u *__restrict__ dst, long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 }  // namespace
@@ -530,7 +571,8 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
       const uint8_t tj = cell_type[j];
       if (tj == T_WALL) f |= NEAR_WALL;
       if (tj == T_INLET) f |= NEAR_INLET;
-      if (t == T_LIQ && (tj == T_GAS || tj == T_INLET)) {
+      if (t == T_LIQ && (tj == T_GAS || tj == T_INLET) &&
+          !(p.debug_flags & FSLBM_DEBUG_NO_LAYER_CHECK)) {
         snprintf(msg, sizeof msg, "cell %lld: liquid next to gas", i);
         return fail(FSLBM_EINVAL, msg);
       }
@@ -607,6 +649,7 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
   c->ws = (char *)device_workspace;
   build_devs(*c);
   c->cur = 0;
+  c->host_step = restore ? restore->step : 0;
   const Dev &d = c->dev[0];
   hipStream_t st = c->stream;
   auto cleanup_fail = [&](int code) {
@@ -661,6 +704,7 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
   sc.share = n_iface > 0 ? sc.bucket / (double)n_iface : 0.0;
   madd(sc.bucket);
   sc.total_mass = ex_value(Mw);
+  sc.mass_ref = sc.total_mass;
   sc.n_live = n_bubbles;
   sc.label_run = 2;  // the first step labels the whole gas region
   sc.n_il_src = (int)n_iface;
@@ -698,33 +742,50 @@ int fslbm_step(void *handle, int32_t n_steps) {
   for (int s = 0; s < n_steps; ++s) {
     const Dev &d = c.dev[c.cur];
     if (c.timing_period > 0 && c.timing_count++ % c.timing_period == 0) {
-      while (c.events.size() < c.used + PH_COUNT + 1) {
-        hipEvent_t e;
-        HIP_TRY(hipEventCreate(&e));
-        c.events.push_back(e);
-      }
-      HIP_TRY(hipEventRecord(c.events[c.used], c.stream));
       for (int ph = 0; ph < PH_COUNT; ++ph) {
+        if (!((c.timing_mask >> ph) & 1u)) {
+          c.L.phase(ph, d, c.cfg, c.stream);
+          continue;
+        }
+        while (c.events.size() < 2 * (c.used + 1)) {
+          hipEvent_t e;
+          HIP_TRY(hipEventCreate(&e));
+          c.events.push_back(e);
+        }
+        if (c.event_phase.size() < c.used + 1) c.event_phase.resize(c.used + 1);
+        HIP_TRY(hipEventRecord(c.events[2 * c.used], c.stream));
         c.L.phase(ph, d, c.cfg, c.stream);
-        HIP_TRY(hipEventRecord(c.events[c.used + 1 + ph], c.stream));
+        HIP_TRY(hipEventRecord(c.events[2 * c.used + 1], c.stream));
+        c.event_phase[c.used] = ph;
+        c.used += 1;
       }
-      c.used += PH_COUNT + 1;
+      c.timed_steps += 1;
     } else {
       for (int ph = 0; ph < PH_COUNT; ++ph) c.L.phase(ph, d, c.cfg, c.stream);
     }
     c.cur ^= 1;
+    c.host_step += 1;
+    if (watchdog_due(c)) {
+      c.L.watchdog(c.dev[c.cur], c.cfg, c.stream);
+      HIP_TRY(hipGetLastError());
+      const int rc = sync_and_check(c);
+      if (rc != FSLBM_OK) return rc;
+    }
   }
   HIP_TRY(hipGetLastError());
   return FSLBM_OK;
 }
 
-int fslbm_set_timing(void *handle, int32_t period) {
+int fslbm_set_timing(void *handle, int32_t period, uint32_t phase_mask) {
   if (!handle) return fail(FSLBM_EINVAL, "handle is NULL");
   if (period < 0) return fail(FSLBM_EINVAL, "timing period < 0");
+  if (phase_mask & ~(uint32_t)FSLBM_PHASE_ALL) return fail(FSLBM_EINVAL, "unknown phase bits");
   Ctx &c = *(Ctx *)handle;
   HIP_TRY(hipStreamSynchronize(c.stream));
   c.timing_period = period;
+  c.timing_mask = phase_mask ? phase_mask : (uint32_t)FSLBM_PHASE_ALL;
   c.timing_count = 0;
+  c.timed_steps = 0;
   c.used = 0;
   return FSLBM_OK;
 }
@@ -734,15 +795,12 @@ int fslbm_get_timing(void *handle, fslbm_timing *out) {
   Ctx &c = *(Ctx *)handle;
   HIP_TRY(hipStreamSynchronize(c.stream));
   double ms[PH_COUNT] = {0};
-  const size_t per = PH_COUNT + 1;
-  const size_t nsteps = c.used / per;
-  for (size_t s = 0; s < nsteps; ++s)
-    for (int ph = 0; ph < PH_COUNT; ++ph) {
-      float t = 0.f;
-      HIP_TRY(hipEventElapsedTime(&t, c.events[s * per + ph], c.events[s * per + ph + 1]));
-      ms[ph] += t;
-    }
-  out->steps = (int64_t)nsteps;
+  for (size_t k = 0; k < c.used; ++k) {
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, c.events[2 * k], c.events[2 * k + 1]));
+    ms[c.event_phase[k]] += t;
+  }
+  out->steps = (int64_t)c.timed_steps;
   out->bulk_ms = ms[PH_BULK];
   out->iface_ms = ms[PH_IFACE];
   out->convert_ms = ms[PH_CONVERT];
@@ -754,6 +812,7 @@ int fslbm_get_timing(void *handle, fslbm_timing *out) {
   for (int ph = 0; ph < PH_COUNT; ++ph) tot += ms[ph];
   out->step_ms = tot;
   c.used = 0;
+  c.timed_steps = 0;
   return FSLBM_OK;
 }
 
@@ -841,6 +900,35 @@ int fslbm_bubbles(void *handle, fslbm_bubble *out, int32_t capacity, int32_t *n_
   if (n_out) *n_out = (int32_t)v.size();
   if ((int32_t)v.size() > capacity) return fail(FSLBM_ECAPACITY, "output capacity too small");
   if (out) std::copy(v.begin(), v.end(), out);
+  return FSLBM_OK;
+}
+
+int fslbm_copy_bandwidth(void *dst, const void *src, size_t bytes, int32_t reps, void *stream,
+                         double *gbs_out) {
+  if (!dst || !src || !gbs_out) return fail(FSLBM_EINVAL, "NULL argument");
+  if (bytes == 0 || bytes % 16 || reps < 1) return fail(FSLBM_EINVAL, "bytes or reps out of range");
+  if (((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+    return fail(FSLBM_EINVAL, "buffers must be 16-byte aligned");
+  const long long n = (long long)(bytes / 16);
+  // about four vectors per thread over the grid
+  const long long want = (n + 4 * 256 - 1) / (4 * 256);
+  const int blocks = (int)(want < 1 ? 1 : (want > 65536 ? 65536 : want));
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  // one untimed pass first
+  k_copy_stream<<<blocks, 256, 0, st>>>((const v4u *)src, (v4u *)dst, n);
+  HIP_TRY(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r) k_copy_stream<<<blocks, 256, 0, st>>>((const v4u *)src, (v4u *)dst, n);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *gbs_out = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;
   return FSLBM_OK;
 }
 
@@ -968,11 +1056,41 @@ int fslbm_batch_step(void *batch, int32_t n_steps) {
     HIP_TRY(hipEventRecord(b.ev_in, st));
     HIP_TRY(hipStreamWaitEvent(b.stream, b.ev_in, 0));
   }
-  for (int s = 0; s < n_steps; ++s) HIP_TRY(hipGraphLaunch(b.exec[(r + s) & 1], b.stream));
+  int rc = FSLBM_OK;
+  int done = 0;
+  for (int s = 0; s < n_steps && rc == FSLBM_OK; ++s) {
+    HIP_TRY(hipGraphLaunch(b.exec[(r + s) & 1], b.stream));
+    done = s + 1;
+    // the watchdog of every member whose check is due after this step
+    bool due = false;
+    for (Ctx *c : b.dom) {
+      c->host_step += 1;
+      if (watchdog_due(*c)) {
+        c->L.watchdog(c->dev[c->cur ^ (done & 1)], c->cfg, b.stream);
+        due = true;
+      }
+    }
+    if (due) {
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipStreamSynchronize(b.stream));
+      for (size_t k = 0; k < b.dom.size() && rc == FSLBM_OK; ++k) {
+        Ctx &c = *b.dom[k];
+        if (!watchdog_due(c)) continue;
+        Scalars sc;
+        HIP_TRY(hipMemcpy(&sc, c.dev[0].sc, sizeof sc, hipMemcpyDeviceToHost));
+        if (sc.err) {
+          // the same message as the domain's own calls give
+          HIP_TRY(hipStreamSynchronize(c.stream));
+          rc = sync_and_check(c);
+          if (rc != FSLBM_OK) g_err = "batch member " + std::to_string(k) + ": " + g_err;
+        }
+      }
+    }
+  }
   HIP_TRY(hipEventRecord(b.ev_out, b.stream));
   for (hipStream_t st : streams) HIP_TRY(hipStreamWaitEvent(st, b.ev_out, 0));
-  for (Ctx *c : b.dom) c->cur ^= (n_steps & 1);
-  return FSLBM_OK;
+  for (Ctx *c : b.dom) c->cur ^= (done & 1);
+  return rc;
 }
 
 int fslbm_batch_info_get(void *batch, fslbm_batch_info *out) {

@@ -80,10 +80,14 @@ struct Scalars {
   int n_roots;           // components of the labelled set (roots listed in nlist)
   int if_prev;           // the interface rows of the previous step are valid
   int pad_;
+  double mass_ref;       // total mass at creation (watchdog drift reference)
 };
 constexpr int ERR_CAPACITY = 1;
 constexpr int ERR_NONFINITE = 2;
 constexpr int ERR_RANGE = 4;
+constexpr int ERR_LAYER = 8;    // a liquid cell next to a gas or inlet cell
+constexpr int ERR_ORPHAN = 16;  // a gas-region cell without a live bubble
+constexpr int ERR_DRIFT = 32;   // total mass drifted beyond the watchdog bound
 
 // Everything a kernel needs, passed by value.  src/dst refer to time t and
 // t+1 of the current step.
@@ -93,7 +97,9 @@ struct Dev {
   int has_walls;
   int max_bubbles;
   int force_topology;
+  int freeze;     // no conversions (cell types stay fixed)
   int collision;
+  double drift_tol;  // watchdog: relative total-mass drift bound (<= 0: off)
   long long N;
   double omega_p, omega_m;
   double sigma, p0, eps, inject;

@@ -116,6 +116,11 @@ static void export_impl(const Dev &d, const LaunchCfg &c, double *out, int what,
 }
 
 template <class P>
+static void watchdog_impl(const Dev &d, const LaunchCfg &c, hipStream_t s) {
+  k_one<K_watchdog<P>><<<c.blocks[G_CELL], K_watchdog<P>::THREADS, 0, s>>>(d);
+}
+
+template <class P>
 static Launchers make_launchers() {
   Launchers L;
   L.phase = phase_impl<P>;
@@ -124,6 +129,7 @@ static Launchers make_launchers() {
   L.init_feq = init_feq_impl<P>;
   L.init_f = init_f_impl<P>;
   L.exportq = export_impl<P>;
+  L.watchdog = watchdog_impl<P>;
   L.store_bytes = (int)sizeof(typename P::S);
   L.real_bytes = (int)sizeof(typename P::R);
   return L;

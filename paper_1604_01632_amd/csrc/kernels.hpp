@@ -805,6 +805,7 @@ struct K_bulk {
     }
   }
   Fx mass;
+  bool bad = false;  // a non-finite density
   const bool in = (long long)w0 + lane < d.N;
   const long long i = in ? (long long)w0 + lane : 0;
   const uint8_t fl = in ? d.flag_src[i] : (uint8_t)T_GAS;
@@ -850,6 +851,7 @@ struct K_bulk {
       R rho, u[3];
       collide<P>(d, f, rho, u);
       if (WITH_MASS) mass.add((double)rho, FX_VOL);
+      bad = !isfinite(rho);
     } else if (t == T_IFACE) {
       const int k = d.islot[i];
       if_load<P>(d.f_if, k, f);
@@ -876,6 +878,8 @@ struct K_bulk {
   } else if (in) {
     d.flag_dst[i] = fl & (STATIC_BITS | TYPE_MASK);
   }
+  if (__ballot(bad) && lane == __ffsll((long long)__ballot(bad)) - 1)
+    atomicOr(&d.sc->err, ERR_NONFINITE);
   if (WITH_MASS) block_fx_add(mass, d.mass_acc, (int)(bk.id % SUB_MASS));
 }
 };
@@ -984,8 +988,11 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
   // no longer separates liquid from gas (no gas / inlet neighbour: filled;
   // no liquid neighbour: emptied); never filled next to an inlet
   uint8_t nf = fl & (STATIC_BITS | TYPE_MASK);
-  if ((phi_new > (R)1 + (R)d.eps || !has_gas) && !(fl & NEAR_INLET)) nf |= CAND_F;
-  if (phi_new < -(R)d.eps || !has_liq) nf |= CAND_E;
+  if (!d.freeze) {
+    if ((phi_new > (R)1 + (R)d.eps || !has_gas) && !(fl & NEAR_INLET)) nf |= CAND_F;
+    if (phi_new < -(R)d.eps || !has_liq) nf |= CAND_E;
+  }
+  if (!isfinite(m_new) || !isfinite(rho)) atomicOr(&d.sc->err, ERR_NONFINITE);
   d.nflag[k] = nf;
   nf_out = nf;
   return (double)m_new;
@@ -2165,6 +2172,55 @@ struct K_bubbles {
     sc->if_prev = 1;  // the interface rows of this step serve the next one
     sc->step += 1;
     if (!isfinite(sc->total_mass)) sc->err |= ERR_NONFINITE;
+  }
+}
+};
+
+// ------------------------------------------------------------ watchdog
+
+// Invariants of the state after a step (launched with the Dev of the next
+// step, so the state is in the source arrays): the interface is a closed
+// layer (no liquid cell next to a gas or inlet cell, Sec. 2.2), every cell
+// of the gas region belongs to a live bubble, interface masses and fill
+// levels are finite; block 0 also checks the drift of the total mass
+// against the mass at creation.  Failures set error bits only.
+template <class P>
+struct K_watchdog {
+  static constexpr int THREADS = 256;
+  static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
+  using R = typename P::R;
+  int err = 0;
+  FSLBM_GRID_STRIDE(i) {
+    const uint8_t t = d.flag_src[i] & TYPE_MASK;
+    if (t == T_LIQ) {
+      int x, y, z;
+      coords(d, i, x, y, z);
+#pragma unroll
+      for (int a = 1; a < Q; ++a) {
+        const long long j = nbr_checked(d, x, y, z, CX[a], CY[a], CZ[a]);
+        if (j < 0) continue;
+        const uint8_t tj = d.flag_src[j] & TYPE_MASK;
+        if (tj == T_GAS || tj == T_INLET) err |= ERR_LAYER;
+      }
+    } else if (in_gas_region(t)) {
+      const int s = d.bslot[i];
+      if (s < 0 || s >= d.max_bubbles || !d.b_live[s]) err |= ERR_ORPHAN;
+    }
+  }
+  // the interface cells of the next step: finite mass and fill level
+  const int n = d.sc->n_il_src;
+  for (int k = bk.id * blockDim.x + threadIdx.x; k < n; k += bk.n * blockDim.x) {
+    const long long i = d.ilist_src[k];
+    const R m = ((const R *)d.mass)[i], ph = ((const R *)d.phi_src)[i];
+    if (!isfinite(m) || !isfinite(ph)) err |= ERR_NONFINITE;
+  }
+  int w = err;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) w |= __shfl_xor(w, m, 64);
+  if (w && __lane_id() == 0) atomicOr(&d.sc->err, w);
+  if (bk.id == 0 && threadIdx.x == 0 && d.drift_tol > 0.0) {
+    const double M = d.sc->total_mass, M0 = d.sc->mass_ref;
+    if (!(fabs(M - M0) <= d.drift_tol * fabs(M0))) atomicOr(&d.sc->err, ERR_DRIFT);
   }
 }
 };

@@ -46,6 +46,8 @@ struct Launchers {
                    hipStream_t s);
   void (*init_f)(const Dev &d, const LaunchCfg &c, const double *src, int a, hipStream_t s);
   void (*exportq)(const Dev &d, const LaunchCfg &c, double *out, int what, hipStream_t s);
+  // invariant checks of the state (the Dev of the next step)
+  void (*watchdog)(const Dev &d, const LaunchCfg &c, hipStream_t s);
   int store_bytes;  // bytes per stored PDF value
   int real_bytes;   // bytes per field value (phi, mass, ...)
 };

@@ -26,7 +26,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Batch, Domain, FslbmError, fslbm_workspace_bytes, PRECISIONS
+from . import Batch, Domain, fslbm_batch_workspace_bytes, fslbm_workspace_bytes, PRECISIONS
 
 
 @dataclass
@@ -50,6 +50,7 @@ class Result:
     steps: int
     bubbles: dict
     scalars: dict
+    error: str = ""  # set when the request was rejected (never admitted)
 
     @property
     def latency(self) -> float:
@@ -57,6 +58,8 @@ class Result:
 
 
 def _finish(slot, t_done) -> Result:
+    """Read out a domain whose steps the device has finished (the caller
+    synchronises before taking t_done)."""
     dom = slot["dom"]
     b = dom.bubbles()
     s = dom.read(())["scalars"]
@@ -65,10 +68,12 @@ def _finish(slot, t_done) -> Result:
 
 
 def summary(results, wall: float) -> dict:
+    rejected = sum(1 for r in results if r.error)
+    results = [r for r in results if not r.error]
     lat = np.array([r.latency for r in results])
     updates = float(sum(r.cells * r.steps for r in results))
     span = max(r.done for r in results) - min(r.arrival for r in results)
-    return dict(requests=len(results), p50_s=float(np.percentile(lat, 50)),
+    return dict(requests=len(results), rejected=rejected, p50_s=float(np.percentile(lat, 50)),
                 p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()),
                 mlups=updates / span / 1e6, span_s=span, wall_s=wall)
 
@@ -76,8 +81,10 @@ def summary(results, wall: float) -> dict:
 class Server:
     """Continuous-batching request loop.
 
-    budget_bytes: device memory the admitted workspaces may use (default:
-    80 % of the free device memory at start); max_active: slots; quantum:
+    budget_bytes: device memory the admitted workspaces and the batch
+    tables may use (default: 80 % of the free device memory at start); a
+    request that could never fit is rejected (a Result with `error` set)
+    and the others keep running; max_active: slots; quantum:
     steps between scheduling decisions (a domain never runs past its
     horizon: a quantum ends at the next horizon).
     """
@@ -121,9 +128,18 @@ class Server:
                         break  # keep the device busy while the scene is built
                     sc = fut.result()
                     need = self._need(sc)
-                    if need > self.budget:
-                        raise FslbmError(-2, f"request {r.id} needs {need} B, budget {self.budget} B")
-                    if used + need > self.budget:
+                    tables = fslbm_batch_workspace_bytes(len(active) + 1)
+                    if need == 0 or need + fslbm_batch_workspace_bytes(1) > self.budget:
+                        waiting.popleft()
+                        t = clock() - t0
+                        why = ("invalid parameters" if need == 0 else
+                               f"needs {need} B of device memory, budget {self.budget} B")
+                        results.append(Result(r.id, r.arrival, t, t, sc.n, 0, {}, {},
+                                              error=f"rejected: {why}"))
+                        if log:
+                            log(f"[serve] request {r.id} rejected: {why}")
+                        continue
+                    if used + need + tables > self.budget:
                         break
                     waiting.popleft()
                     dom = Domain.from_scene(sc, self.precision, **self.overrides)
@@ -148,7 +164,8 @@ class Server:
                 done = [s for s in active if s["left"] == 0]
                 if done:
                     for s in done:
-                        res = _finish(s, clock() - t0)  # synchronises
+                        s["dom"].sync()  # its last quantum has finished on the device
+                        res = _finish(s, clock() - t0)
                         results.append(res)
                         s["dom"].close()
                         used -= s["need"]
@@ -194,6 +211,7 @@ def run_fifo(requests, precision="fp32", clock=time.perf_counter, overrides=None
                 dom.step(q)
                 dom.sync()
                 left -= q
+            dom.sync()
             res = _finish(dict(req=r, dom=dom, admitted=admitted), clock() - t0)
             results.append(res)
             dom.close()

@@ -192,3 +192,29 @@ def test_invariants_every_step(oracle_lib):
             v = np.sum(np.where(d["cell_type"][sel] == IFACE, 1.0 - d["phi"][sel], 1.0))
             assert v == pytest.approx(b["volume"][k], rel=1e-12)
             assert np.count_nonzero(sel) == b["n_cells"][k]
+
+
+def test_frozen_conversions_keep_the_geometry(oracle_lib):
+    """With conversions frozen no interface cell is filled or emptied: the
+    cell types and bubble IDs stay those of the start, no excess mass
+    appears and the total mass is conserved to round-off, while the fill
+    levels still move with the mass exchange."""
+    sc = scenes.merge_ids_if_touching(scenes.random_blobs(n=(20, 18, 16), nblob=4, seed=5))
+    o = oracle_lib.Oracle.from_scene(sc, freeze_conversions=1)
+    m0 = o.scalars()["total_mass"]
+    phi0 = sc.phi.copy()
+    for _ in range(3):
+        o.step(10)
+        d = o.read()
+        assert np.array_equal(d["cell_type"], sc.cell_type)
+        assert np.array_equal(d["bubble_id"], np.where(np.isin(sc.cell_type, (GAS, IFACE, 4)),
+                                                       sc.bubble_id, -1))
+        s = o.scalars()
+        assert s["bucket"] == 0.0 and s["n_topology"] == 0
+        assert abs(s["total_mass"] - m0) <= 1e-13 * m0
+    it = sc.cell_type == IFACE
+    assert np.max(np.abs(d["phi"][it] - phi0[it])) > 1e-3
+    # unfrozen, the same scene converts cells within those steps
+    u = oracle_lib.Oracle.from_scene(sc)
+    u.step(30)
+    assert not np.array_equal(u.read()["cell_type"], sc.cell_type)
