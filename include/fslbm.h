@@ -297,6 +297,22 @@ int fslbm_batch_create(void *const *handles, int32_t n, const char *tuning_cache
                        void *device_workspace, size_t workspace_bytes, void *stream,
                        void **out_batch);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * batched form of fslbm_batch_create with its tables in a static device
+ * array of the library (4 MiB per GPU, held until the process ends) instead
+ * of a caller workspace.  No device memory is allocated and no stream,
+ * event or graph is created: every domain must have been created on
+ * `stream`, and each batch step is the plain launch of the step kernels on
+ * it (no tuning: 256-thread stream-collide blocks, domains as given).  The
+ * domains compute bit for bit what they compute alone or in any batch.
+ * At most about 4000 domains (EINVAL beyond the array, with the sizes in
+ * the message).  All such batches on one GPU share the one array: creating
+ * one overwrites the tables of the one before, which must not be stepped
+ * again; calls that overlap on one GPU race.  Use fslbm_batch_step and
+ * fslbm_batch_destroy on the returned batch. */
+int fslbm_batch_create_noalloc(void *const *handles, int32_t n, void *stream, void **out_batch);
+
 /* Enqueue n_steps >= 0 steps of every domain of the batch (n_steps graph
  * launches).  Asynchronous errors of a domain are reported by fslbm_sync,
  * fslbm_read_fields or fslbm_bubbles on its handle. */

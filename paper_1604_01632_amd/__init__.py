@@ -109,6 +109,9 @@ def lib() -> C.CDLL:
         L.fslbm_batch_create.restype = C.c_int
         L.fslbm_batch_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_char_p, P,
                                          C.c_size_t, P, C.POINTER(C.c_void_p)]
+        L.fslbm_batch_create_noalloc.restype = C.c_int
+        L.fslbm_batch_create_noalloc.argtypes = [C.POINTER(C.c_void_p), C.c_int32, P,
+                                                 C.POINTER(C.c_void_p)]
         L.fslbm_batch_step.restype = C.c_int
         L.fslbm_batch_step.argtypes = [P, C.c_int32]
         L.fslbm_batch_info_get.restype = C.c_int
@@ -324,6 +327,20 @@ def fslbm_batch_create(handles, tuning_cache_path, workspace, stream=None):
     path = None if tuning_cache_path is None else str(tuning_cache_path).encode()
     _check(lib().fslbm_batch_create(arr, len(handles), path, C.c_void_p(workspace.data_ptr()),
                                     workspace.numel(), C.c_void_p(st.cuda_stream), C.byref(b)))
+    return b
+
+
+def fslbm_batch_create_noalloc(handles, stream=None):
+    """Batch over the given handles with its tables in the library's static
+    device array (no workspace); every domain must have been created on
+    `stream` (default: the current stream)."""
+    import torch
+
+    arr = (C.c_void_p * len(handles))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    st = stream if stream is not None else torch.cuda.current_stream()
+    b = C.c_void_p()
+    _check(lib().fslbm_batch_create_noalloc(arr, len(handles), C.c_void_p(st.cuda_stream),
+                                            C.byref(b)))
     return b
 
 

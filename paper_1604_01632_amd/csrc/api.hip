@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -12,6 +13,14 @@
 #include "launch.hpp"
 
 using namespace fslbm;
+
+// The batch tables of fslbm_batch_create_noalloc: a static device array
+// (one copy per GPU, kept until the process ends).  In host code `scratch`
+// only names the symbol; its device address on the current device comes
+// from hipGetSymbolAddress, once per device (scratch_address below), and
+// only that address is used (kernel arguments, copies).
+static constexpr size_t SCRATCH_BYTES = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
 
 namespace {
 
@@ -274,6 +283,9 @@ struct Batch {
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   fslbm_batch_info info{};
+  // tables in the library's static scratch array: no own stream, events or
+  // graphs; steps are plain launches on the caller's stream
+  bool in_scratch = false;
 };
 
 size_t batch_bytes(int nd) {
@@ -341,6 +353,26 @@ int batch_capture(Batch &b) {
     HIP_TRY(hipStreamEndCapture(b.stream, &b.graph[r]));
     HIP_TRY(hipGraphInstantiate(&b.exec[r], b.graph[r], nullptr, nullptr, 0));
   }
+  return FSLBM_OK;
+}
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the scratch array on the current device.
+int scratch_address(void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(FSLBM_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || ((uintptr_t)ptr & 255)) return fail(FSLBM_EDEVICE, "scratch array not aligned");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
   return FSLBM_OK;
 }
 
@@ -413,6 +445,12 @@ void batch_order(Batch &b, const std::vector<Ctx *> &given, int order) {
 
 void batch_free(Batch *b) {
   if (!b) return;
+  if (b->in_scratch) {
+    // nothing of its own on the device: wait for its work and drop the host part
+    hipStreamSynchronize(b->stream);
+    delete b;
+    return;
+  }
   if (b->stream) hipStreamSynchronize(b->stream);
   batch_drop_graphs(*b);
   if (b->ev_in) hipEventDestroy(b->ev_in);
@@ -1028,6 +1066,49 @@ int fslbm_batch_create(void *const *handles, int32_t n, const char *tuning_cache
   return FSLBM_OK;
 }
 
+int fslbm_batch_create_noalloc(void *const *handles, int32_t n, void *stream, void **out_batch) {
+  if (!out_batch) return fail(FSLBM_EINVAL, "out_batch is NULL");
+  *out_batch = nullptr;
+  if (!handles || n < 1) return fail(FSLBM_EINVAL, "no handles");
+  if (batch_bytes(n) > SCRATCH_BYTES)
+    return fail(FSLBM_EINVAL, "too many domains for the static batch tables: " + std::to_string(n) +
+                                  " domains need " + std::to_string(batch_bytes(n)) +
+                                  " bytes, the array holds " + std::to_string(SCRATCH_BYTES));
+  std::vector<Ctx *> given(n);
+  for (int k = 0; k < n; ++k) {
+    if (!handles[k]) return fail(FSLBM_EINVAL, "a handle is NULL");
+    given[k] = (Ctx *)handles[k];
+    for (int j = 0; j < k; ++j)
+      if (given[j] == given[k]) return fail(FSLBM_EINVAL, "a handle is listed twice");
+    if (given[k]->P.precision != given[0]->P.precision)
+      return fail(FSLBM_EINVAL, "all domains of a batch must have the same precision");
+    if (given[k]->stream != (hipStream_t)stream)
+      return fail(FSLBM_EINVAL, "every domain must have been created on the batch's stream");
+  }
+  void *ptr = nullptr;
+  if (int rc = scratch_address(&ptr)) return rc;
+  Batch *b = new Batch();
+  b->in_scratch = true;
+  b->precision = given[0]->P.precision;
+  b->L = given[0]->L;
+  b->user_stream = (hipStream_t)stream;
+  b->stream = (hipStream_t)stream;
+  b->ws = (char *)ptr;
+  b->dom = given;
+  long long cells = 0;
+  for (Ctx *c : given) cells += c->N;
+  b->info.cells = cells;
+  b->info.bulk_threads = 256;
+  int rc = batch_tables(*b, 256);
+  if (rc != FSLBM_OK) {
+    delete b;
+    return rc;
+  }
+  *out_batch = b;
+  g_err.clear();
+  return FSLBM_OK;
+}
+
 int fslbm_batch_step(void *batch, int32_t n_steps) {
   if (!batch) return fail(FSLBM_EINVAL, "batch is NULL");
   if (n_steps < 0) return fail(FSLBM_EINVAL, "n_steps < 0");
@@ -1042,24 +1123,31 @@ int fslbm_batch_step(void *batch, int32_t n_steps) {
   int r = r0;
   if (!same) {
     int rc = batch_tables(b, b.info.bulk_threads);
-    if (rc == FSLBM_OK) rc = batch_capture(b);
+    if (rc == FSLBM_OK && !b.in_scratch) rc = batch_capture(b);
     if (rc != FSLBM_OK) return rc;
     r = 0;
   }
   // order after the work already queued on the caller's and the domains'
-  // streams, and before whatever they queue next
+  // streams, and before whatever they queue next (a batch in the scratch
+  // array runs on the one stream of the caller and its domains)
   std::vector<hipStream_t> streams{b.user_stream};
-  for (Ctx *c : b.dom)
-    if (std::find(streams.begin(), streams.end(), c->stream) == streams.end())
-      streams.push_back(c->stream);
-  for (hipStream_t st : streams) {
-    HIP_TRY(hipEventRecord(b.ev_in, st));
-    HIP_TRY(hipStreamWaitEvent(b.stream, b.ev_in, 0));
+  if (!b.in_scratch) {
+    for (Ctx *c : b.dom)
+      if (std::find(streams.begin(), streams.end(), c->stream) == streams.end())
+        streams.push_back(c->stream);
+    for (hipStream_t st : streams) {
+      HIP_TRY(hipEventRecord(b.ev_in, st));
+      HIP_TRY(hipStreamWaitEvent(b.stream, b.ev_in, 0));
+    }
   }
   int rc = FSLBM_OK;
   int done = 0;
   for (int s = 0; s < n_steps && rc == FSLBM_OK; ++s) {
-    HIP_TRY(hipGraphLaunch(b.exec[(r + s) & 1], b.stream));
+    if (b.in_scratch) {
+      for (int ph = 0; ph < PH_COUNT; ++ph) b.L.batch_phase(ph, b.cfg[(r + s) & 1], b.stream);
+    } else {
+      HIP_TRY(hipGraphLaunch(b.exec[(r + s) & 1], b.stream));
+    }
     done = s + 1;
     // the watchdog of every member whose check is due after this step
     bool due = false;
@@ -1087,8 +1175,10 @@ int fslbm_batch_step(void *batch, int32_t n_steps) {
       }
     }
   }
-  HIP_TRY(hipEventRecord(b.ev_out, b.stream));
-  for (hipStream_t st : streams) HIP_TRY(hipStreamWaitEvent(st, b.ev_out, 0));
+  if (!b.in_scratch) {
+    HIP_TRY(hipEventRecord(b.ev_out, b.stream));
+    for (hipStream_t st : streams) HIP_TRY(hipStreamWaitEvent(st, b.ev_out, 0));
+  }
   for (Ctx *c : b.dom) c->cur ^= (done & 1);
   return rc;
 }
