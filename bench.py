@@ -430,6 +430,8 @@ def main() -> int:
                          "(no roofline figure)")
     ap.add_argument("--no-phase-breakdown", dest="phase_breakdown", action="store_false",
                     help="skip the rerun of the window with every phase timed")
+    ap.add_argument("--no-trigger-compare", dest="trigger_compare", action="store_false",
+                    help="skip the rerun of the window with the anti-parallel-normals trigger")
     ap.add_argument("--no-copy-probe", action="store_true",
                     help="skip the achievable-bandwidth copy probe")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -470,10 +472,10 @@ def main() -> int:
     start = args.start_step if args.start_step >= 0 else (RUPTURE_START if args.workload == "p1" else 0)
     N = sc.n
 
-    def run_window(phases, period):
+    def run_window(phases, period, **over):
         """Evolve a fresh domain to `start`, warm up, then time the window;
         returns the measurements and the domain."""
-        dom = F.Domain.from_scene(sc, args.precision)
+        dom = F.Domain.from_scene(sc, args.precision, **over)
         if start:
             dom.step(start)
         dom.step(args.warmup)
@@ -493,9 +495,10 @@ def main() -> int:
         wall = time.perf_counter() - t0
         T = F.fslbm_get_timing(dom.handle)
         F.fslbm_set_timing(dom.handle, 0)
-        r1 = dom.read(("cell_type",))
+        r1 = dom.read(("cell_type", "bubble_id"))
+        end_ids = r1.pop("bubble_id")
         return dict(gpu_ms=ev0.elapsed_time(ev1), wall=wall, T=T, r0=r0, r1=r1, b0=b0,
-                    b1=dom.bubbles()), dom
+                    b1=dom.bubbles(), end_ids=end_ids), dom
 
     log(f"[bench] {sc.name}: {sc.nx}x{sc.ny}x{sc.nz} ({N} cells) {args.precision}; evolve to step "
         f"{start}, warm-up {args.warmup}, timed {args.steps}")
@@ -540,6 +543,31 @@ def main() -> int:
                   ("bulk_ms", "iface_ms", "convert_ms", "excess_ms", "gather_ms", "label_ms",
                    "bubbles_ms")}
         log(f"[bench] per-step phase times (us, same window rerun, every phase timed): {phases}")
+    triggers = None
+    if args.trigger_compare:
+        # the same window with the paper's split trigger (anti-parallel
+        # normals, Sec. 2.3.2) instead of the exact one: how often each
+        # starts a labelling run, and whether the normals trigger left a
+        # split undetected (fewer bubbles, or a different state at the end)
+        mn, dom = run_window(None, 0, split_trigger=F.TRIGGER_NORMALS, trigger_cos=-0.5)
+        end_n = dom.read(("cell_type", "bubble_id"))
+        dom.close()
+        del dom
+        torch.cuda.empty_cache()
+        runs_e = int(s1["n_label_runs"] - s0["n_label_runs"])
+        runs_n = int(mn["r1"]["scalars"]["n_label_runs"] - mn["r0"]["scalars"]["n_label_runs"])
+        same = bool(np.array_equal(end_n["cell_type"], m["r1"]["cell_type"])
+                    and np.array_equal(end_n["bubble_id"], m["end_ids"]))
+        triggers = {
+            "exact": {"label_runs": runs_e, "per_1000_steps": round(1000.0 * runs_e / args.steps, 1),
+                      "bubbles_end": int(len(m["b1"]["id"])), "ms_per_step": round(ms_per_step, 4)},
+            "normals": {"label_runs": runs_n, "per_1000_steps": round(1000.0 * runs_n / args.steps, 1),
+                        "bubbles_end": int(len(mn["b1"]["id"])),
+                        "ms_per_step": round(max(mn["gpu_ms"], mn["wall"] * 1e3) / args.steps, 4),
+                        "trigger_cos": -0.5},
+            "same_state_at_end": same,
+        }
+        log(f"[bench] triggers over the window: {triggers}")
     copy = copy_bandwidth_context() if not args.no_copy_probe else None
     if copy:
         log(f"[bench] streaming copy: {copy['GBs']} GB/s ({copy['frac_of_peak']} of peak)")
@@ -574,6 +602,7 @@ def main() -> int:
             "whole_step_bytes_per_fluid_cell": b_alg,
             "bulk_sampled_steps": int(T["steps"]),
             "phase_us": phases,
+            "split_triggers": triggers,
             "achievable_copy": copy,
         },
         "roofline": {

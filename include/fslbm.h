@@ -109,8 +109,26 @@ typedef struct {
                              creation) tolerated by the watchdog; <= 0: not
                              checked */
   int32_t debug_flags;    /* FSLBM_DEBUG_* bits (testing only) */
-  int32_t pad_;
+  int32_t split_trigger;  /* FSLBM_TRIGGER_EXACT (default) or
+                             FSLBM_TRIGGER_NORMALS */
+  double trigger_cos;     /* FSLBM_TRIGGER_NORMALS: two unit normals are
+                             anti-parallel when their dot product is below
+                             this value (e.g. -0.5) */
 } fslbm_params;
+
+/* What starts the connected-component labelling of a bubble (Sec. 2.3).
+ * Merges are found exactly in both cases: a cell that joins the gas region
+ * next to another bubble's cell (Sec. 2.3.1).  Splits (Sec. 2.3.2):
+ *   EXACT    a cell that leaves the gas region and whose remaining
+ *            gas-region neighbours are not connected inside its 3x3x3
+ *            block, or that touches another such cell: never misses a
+ *            split (the result equals labelling every step);
+ *   NORMALS  the paper's test: a cell that turns liquid and has, among its
+ *            18 neighbours, two interface cells of the same bubble whose
+ *            normals (fill-level gradients of the step) are anti-parallel,
+ *            n1.n2 < trigger_cos |n1| |n2|.  Cheaper in labelling runs, but
+ *            a split it does not see stays undetected until it fires. */
+enum { FSLBM_TRIGGER_EXACT = 0, FSLBM_TRIGGER_NORMALS = 1 };
 
 /* debug_flags: accept a liquid cell next to a gas or inlet cell at
  * creation (for tests of the watchdog; the step is not defined on such a
@@ -145,6 +163,8 @@ typedef struct {
   double total_mass;   /* sum over liquid rho + interface m + bucket, FP64,
                           of the last step */
   int64_t n_topology;  /* steps in which a merge or split created bubbles */
+  int64_t n_label_runs; /* steps in which the labelling ran (the trigger
+                           fired, or the first step) */
 } fslbm_scalars;
 
 /* Exact device workspace size for these parameters (0 on invalid params). */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfslbm.so")
 FSLBM_OK, FSLBM_EINVAL, FSLBM_ENOMEM, FSLBM_EDEVICE, FSLBM_ENUMERIC, FSLBM_ECAPACITY = 0, -1, -2, -3, -4, -5
 FP64, FP32, FP16DEV = 0, 1, 2
 DEBUG_NO_LAYER_CHECK = 1
+TRIGGER_EXACT, TRIGGER_NORMALS = 0, 1
 PHASES = ("iface", "bulk", "convert", "excess", "gather", "label", "bubbles")
 PHASE_BITS = {name: 1 << k for k, name in enumerate(PHASES)}
 BGK, TRT = 0, 1
@@ -38,7 +39,8 @@ class Params(C.Structure):
                 ("inject_rate", C.c_double), ("max_bubbles", C.c_int32),
                 ("force_topology", C.c_int32), ("freeze_conversions", C.c_int32),
                 ("watchdog_every", C.c_int32), ("watchdog_drift", C.c_double),
-                ("debug_flags", C.c_int32), ("pad_", C.c_int32)]
+                ("debug_flags", C.c_int32), ("split_trigger", C.c_int32),
+                ("trigger_cos", C.c_double)]
 
 
 class BubbleInit(C.Structure):
@@ -53,7 +55,8 @@ class Bubble(C.Structure):
 
 class Scalars(C.Structure):
     _fields_ = [("step", C.c_int64), ("next_id", C.c_int32), ("n_bubbles", C.c_int32),
-                ("bucket", C.c_double), ("total_mass", C.c_double), ("n_topology", C.c_int64)]
+                ("bucket", C.c_double), ("total_mass", C.c_double), ("n_topology", C.c_int64),
+                ("n_label_runs", C.c_int64)]
 
 
 class BatchInfo(C.Structure):
@@ -152,6 +155,8 @@ def make_params(d: dict) -> Params:
     p.watchdog_every = int(d.get("watchdog_every", 0))
     p.watchdog_drift = float(d.get("watchdog_drift", 0.0))
     p.debug_flags = int(d.get("debug_flags", 0))
+    p.split_trigger = int(d.get("split_trigger", TRIGGER_EXACT))
+    p.trigger_cos = float(d.get("trigger_cos", -0.5))
     return p
 
 
@@ -214,7 +219,8 @@ def fslbm_read_fields(handle, N: int, what=("cell_type", "phi", "mass", "f", "bu
                                  C.byref(sc))
     _check(rc)
     out["scalars"] = dict(step=sc.step, next_id=sc.next_id, n_bubbles=sc.n_bubbles,
-                          bucket=sc.bucket, total_mass=sc.total_mass, n_topology=sc.n_topology)
+                          bucket=sc.bucket, total_mass=sc.total_mass, n_topology=sc.n_topology,
+                          n_label_runs=sc.n_label_runs)
     return out
 
 

@@ -56,7 +56,7 @@ enum Arr {
   A_F0, A_F1, A_FLAG0, A_FLAG1, A_PHI0, A_PHI1, A_MASS, A_RHOI, A_EXCESS, A_BSLOT, A_LAB,
   A_AUX0, A_AUX2, A_BID, A_BFLAGS, A_BLIVE, A_BRMIN, A_BRMAX, A_BKEPT, A_BAFFECT, A_NEWROOTS,
   A_NEWSLOT, A_BVSTAR, A_BVOL, A_BP, A_BRATIO, A_BNGAS, A_BNIFACE, A_BVACC, A_CACC,
-  A_SCALARS, A_MASSACC, A_BUCKETACC, A_ILIST0, A_ILIST1, A_CLIST, A_NLIST, A_MARK, A_GASV, A_NMASK, A_TILECOUNT, A_TILEOFF,
+  A_SCALARS, A_MASSACC, A_BUCKETACC, A_ILIST0, A_ILIST1, A_CLIST, A_NLIST, A_MARK, A_GASV, A_NMASK, A_NRM, A_TILECOUNT, A_TILEOFF,
   A_FIF0, A_FIF1, A_NFLAG, A_ISLOT0, A_ISLOT1, A_COUNT
 };
 
@@ -87,6 +87,7 @@ Layout make_layout(const fslbm_params &p, const Launchers &L) {
   sz[A_MARK] = ((N + 3) / 4) * 4;
   sz[A_GASV] = N * L.real_bytes;
   sz[A_NMASK] = N * 4;
+  sz[A_NRM] = p.split_trigger == FSLBM_TRIGGER_NORMALS ? 3 * N * 4 : 0;
   sz[A_TILECOUNT] = sz[A_TILEOFF] = ((N + 4095) / 4096) * 4;
   sz[A_FIF0] = sz[A_FIF1] = N * (((size_t)Q * L.store_bytes + 15) / 16 * 16);  // one padded row per slot
   sz[A_NFLAG] = N;
@@ -121,6 +122,10 @@ const char *check_params(const fslbm_params *p) {
     return "freeze_conversions must be 0 or 1";
   if (p->watchdog_every < 0) return "watchdog_every must be >= 0";
   if (p->debug_flags & ~FSLBM_DEBUG_NO_LAYER_CHECK) return "unknown debug_flags bits";
+  if (p->split_trigger != FSLBM_TRIGGER_EXACT && p->split_trigger != FSLBM_TRIGGER_NORMALS)
+    return "unknown split_trigger";
+  if (p->split_trigger == FSLBM_TRIGGER_NORMALS && !(p->trigger_cos >= -1.0 && p->trigger_cos <= 1.0))
+    return "trigger_cos must lie in [-1, 1]";
   return nullptr;
 }
 
@@ -166,6 +171,8 @@ void build_devs(Ctx &c) {
   d.max_bubbles = c.P.max_bubbles;
   d.force_topology = c.P.force_topology;
   d.freeze = c.P.freeze_conversions;
+  d.split_trigger = c.P.split_trigger;
+  d.trigger_cos = c.P.trigger_cos;
   d.drift_tol = c.P.watchdog_drift;
   d.collision = c.P.collision;
   d.N = c.N;
@@ -209,6 +216,7 @@ void build_devs(Ctx &c) {
   d.mark = at<unsigned>(ws, lay, A_MARK);
   d.gasv = ws + lay.off[A_GASV];
   d.nmask = at<uint32_t>(ws, lay, A_NMASK);
+  d.nrm = at<float>(ws, lay, A_NRM);
   d.tilecount = at<int32_t>(ws, lay, A_TILECOUNT);
   d.tileoff = at<int32_t>(ws, lay, A_TILEOFF);
   d.nflag = at<uint8_t>(ws, lay, A_NFLAG);
@@ -909,6 +917,7 @@ int fslbm_read_fields(void *handle, uint8_t *cell_type, double *phi, double *mas
     scalars->bucket = sc.bucket;
     scalars->total_mass = sc.total_mass;
     scalars->n_topology = sc.n_topology;
+    scalars->n_label_runs = sc.n_label_runs;
   }
   return FSLBM_OK;
 }

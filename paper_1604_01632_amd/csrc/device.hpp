@@ -62,7 +62,8 @@ constexpr int NACC = 2 * EX_WORDS + 4;
 struct Scalars {
   long long step;
   long long n_iface;     // interface cells at the end of the last step
-  long long n_topology;  // steps with a labelling run
+  long long n_topology;  // steps in which a labelling run created bubbles
+  long long n_label_runs;  // steps with a labelling run
   double bucket;         // orphan excess mass after the last step's phase D
   double share;          // bucket / n_iface, added to every interface cell next step
   double total_mass;
@@ -98,6 +99,8 @@ struct Dev {
   int max_bubbles;
   int force_topology;
   int freeze;     // no conversions (cell types stay fixed)
+  int split_trigger;  // 0 exact 3x3x3 test, 1 anti-parallel normals
+  double trigger_cos;
   int collision;
   double drift_tol;  // watchdog: relative total-mass drift bound (<= 0: off)
   long long N;
@@ -126,9 +129,11 @@ struct Dev {
   int32_t *ilist_src, *ilist_dst, *clist, *nlist;
   unsigned *mark;
   // per interface-list slot: gas density (FP64) or its deviation from 1,
-  // and the bit mask of directions to reconstruct
+  // the bit mask of directions to reconstruct, and the unit normal (split
+  // trigger by normals only)
   void *gasv;
   uint32_t *nmask;
+  float *nrm;  // [3][N] by slot of the list of t
   // per tile of the ordered interface-list build: counts and offsets
   int32_t *tilecount, *tileoff;
   // outputs of the interface kernel by list slot (post-collision values,

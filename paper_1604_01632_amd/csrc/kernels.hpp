@@ -716,6 +716,15 @@ struct K_geom {
     }
     ((R *)d.gasv)[k] = g;
     d.nmask[k] = mask;
+    if (d.split_trigger == 1) {
+      // unit normal for the split trigger by anti-parallel normals
+      const float len = (float)sqrt((double)(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]));
+      const float inv = len > 0.0f ? 1.0f / len : 0.0f;
+      const long long N = d.N;
+      d.nrm[k] = (float)nv[0] * inv;
+      d.nrm[N + k] = (float)nv[1] * inv;
+      d.nrm[2 * N + k] = (float)nv[2] * inv;
+    }
   }
 }
 };
@@ -1278,6 +1287,37 @@ __device__ __forceinline__ bool split_possible(const uint8_t (&n1)[27], const ui
   return false;
 }
 
+// The split test of the paper (Sec. 2.3.2): among the 18 neighbours of the
+// cell that turned liquid, two interface cells of its bubble (interface at
+// t and at t + 1, so that they have a normal of this step) whose unit
+// normals point in opposite directions, n1.n2 < trigger_cos.
+__device__ __forceinline__ bool antiparallel_normals(const Dev &d, int x, int y, int z, int slot,
+                                                     const uint8_t (&n1)[27],
+                                                     const uint8_t (&n0)[27]) {
+  float nx[18], ny[18], nz[18];
+  int cnt = 0;
+  const long long N = d.N;
+#pragma unroll
+  for (int p = 0; p < 27; ++p) {
+    const int dx = p % 3 - 1, dy = (p / 3) % 3 - 1, dz = p / 9 - 1;
+    const int l1 = (dx != 0) + (dy != 0) + (dz != 0);
+    if (l1 == 0 || l1 == 3) continue;
+    if ((n1[p] & TYPE_MASK) != T_IFACE || (n0[p] & TYPE_MASK) != T_IFACE) continue;
+    const long long j = nbr(d, x, y, z, dx, dy, dz);
+    if (d.bslot[j] != slot) continue;
+    const int k = d.islot[j];
+    nx[cnt] = d.nrm[k];
+    ny[cnt] = d.nrm[N + k];
+    nz[cnt] = d.nrm[2 * N + k];
+    ++cnt;
+  }
+  const float c = (float)d.trigger_cos;
+  for (int a = 0; a < cnt; ++a)
+    for (int b = a + 1; b < cnt; ++b)
+      if (nx[a] * nx[b] + ny[a] * ny[b] + nz[a] * nz[b] < c) return true;
+  return false;
+}
+
 template <class P>
 struct K_excess {
   static constexpr int THREADS = 256;
@@ -1339,7 +1379,8 @@ struct K_excess {
         mass[i] = rho_i;
         ((R *)d.phi_src)[i] = (R)1;
         ((R *)d.phi_dst)[i] = (R)1;
-        if (split_possible(n1, n0)) {
+        if (d.split_trigger == 1 ? antiparallel_normals(d, x, y, z, slot, n1, n0)
+                                 : split_possible(n1, n0)) {
           trig = true;
           atomicOr(&d.b_affect[slot], 1);
         }
@@ -2161,6 +2202,7 @@ struct K_bubbles {
   if (threadIdx.x == 0) {
     Scalars *sc = d.sc;
     sc->n_live = live;
+    if (sc->label_run) sc->n_label_runs += 1;
     sc->label_run = 0;
     // the lists of the next step
     sc->n_il_src = sc->n_il_dst;
