@@ -254,20 +254,23 @@ def bench_batched(args) -> int:
     return 0
 
 
-def _bubble_errors(ref: dict, got: dict) -> dict:
+def _bubble_errors(sc, ref, got) -> dict:
     """Bubble count of `got` against `ref` and the largest relative volume
-    error, bubbles matched by ID when both tables hold the same IDs, else by
-    volume rank."""
-    same_ids = ref["id"].tolist() == got["id"].tolist()
-    if same_ids:
-        rv, gv = np.asarray(ref["volume"]), np.asarray(got["volume"])
-    else:
-        rv, gv = np.sort(ref["volume"])[::-1], np.sort(got["volume"])[::-1]
-        k = min(len(rv), len(gv))
-        rv, gv = rv[:k], gv[:k]
-    err = float(np.max(np.abs(gv - rv) / np.abs(rv))) if len(rv) else 0.0
-    return {"bubbles": int(len(got["id"])), "bubbles_fp64": int(len(ref["id"])),
-            "same_ids": bool(same_ids), "max_rel_volume_error": err}
+    error, bubbles paired by centroid (the ID sequences of the forms differ
+    when they see different numbers of merges and splits)."""
+    from tests.parity import match_by_centroid
+
+    rb, gb = ref[0], got[0]
+    out = {"bubbles": int(len(gb["id"])), "bubbles_fp64": int(len(rb["id"])),
+           "same_ids": rb["id"].tolist() == gb["id"].tolist(), "max_rel_volume_error": None}
+    if len(rb["id"]) == len(gb["id"]):
+        m = match_by_centroid(ref[2], got[2], (sc.nz, sc.ny, sc.nx))
+        if m is not None:
+            err = np.abs(gb["volume"][m] - rb["volume"]) / rb["volume"]
+            out["max_rel_volume_error"] = float(err.max()) if len(err) else 0.0
+    out["total_volume_rel_error"] = float(abs(gb["volume"].sum() - rb["volume"].sum())
+                                          / max(rb["volume"].sum(), 1e-300))
+    return out
 
 
 def bench_forms(args) -> int:
@@ -302,8 +305,10 @@ def bench_forms(args) -> int:
         dom.close()
         del dom
         torch.cuda.empty_cache()
+    from tests.parity import centroids
+
     accuracy = {}
-    for name, horizon in (("c2", args.c2_steps), ("c3", args.c3_steps)):
+    for name, horizon in (("c2", args.c2_steps), ("c3", args.c3_steps), ("c3d", args.c3d_steps)):
         cs = scenes.config(name)
         res = {}
         for prec in forms:
@@ -316,15 +321,22 @@ def bench_forms(args) -> int:
                 dom.sync()
                 done += n
                 log(f"[bench] {name} {prec}: {done}/{horizon} steps")
-            s = dom.read(("cell_type",))["scalars"]
-            res[prec] = (dom.bubbles(), abs(s["total_mass"] - m0) / m0)
+            r = dom.read(("bubble_id",))
+            s = r["scalars"]
+            b = dom.bubbles()
+            res[prec] = (b, abs(s["total_mass"] - m0) / m0,
+                         centroids(r["bubble_id"], b["id"], (cs.nz, cs.ny, cs.nx)),
+                         int(s["n_topology"]))
             dom.close()
             del dom
             torch.cuda.empty_cache()
-        accuracy[name] = {"horizon": horizon, "fp64_mass_drift": res["fp64"][1]}
+        accuracy[name] = {"horizon": horizon, "fp64_mass_drift": res["fp64"][1],
+                          "fp64_bubbles": int(len(res["fp64"][0]["id"])),
+                          "fp64_merges_splits": res["fp64"][3]}
         for prec in ("fp32", "fp16dev"):
-            e = _bubble_errors(res["fp64"][0], res[prec][0])
+            e = _bubble_errors(cs, res["fp64"], res[prec])
             e["mass_drift"] = res[prec][1]
+            e["merges_splits"] = res[prec][3]
             accuracy[name][prec] = e
         log(f"[bench] {name}: {accuracy[name]}")
     out = {
@@ -334,7 +346,8 @@ def bench_forms(args) -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "precision forms: p1 256^3 thread rupture in fp64, fp32 and "
                                "fp16-deviation storage (value: fp32); accuracy of fp32 and "
-                               "fp16dev against fp64 at the c2 and c3 horizons",
+                               "fp16dev against fp64 at the c2, c3 and c3d (detaching orifice) "
+                               "horizons, bubbles paired by centroid",
                    "p1": speed,
                    "speedup_vs_fp64": {p: round(speed[p]["mlups"] / speed["fp64"]["mlups"], 2)
                                        for p in forms},
@@ -444,6 +457,8 @@ def main() -> int:
     ap.add_argument("--quantum", type=int, default=100, help="served workload: steps per decision")
     ap.add_argument("--c2-steps", type=int, default=20000, help="forms workload: c2 horizon")
     ap.add_argument("--c3-steps", type=int, default=50000, help="forms workload: c3 horizon")
+    ap.add_argument("--c3d-steps", type=int, default=7000,
+                    help="forms workload: horizon of the detaching orifice variant")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "

@@ -159,7 +159,7 @@ struct orc {
   uint8_t *type2;
   double *f2, *m2, *phi2, *rho2, *u2, *excess;
   int32_t *id2;
-  uint8_t *filled, *emptied0, *emptied;
+  uint8_t *filled, *emptied0, *emptied, *capped;
   int32_t *label;
 };
 
@@ -506,6 +506,7 @@ orc *orc_create(const orc_params *p, const uint8_t *type, const double *phi, con
   o->filled = malloc(N);
   o->emptied0 = malloc(N);
   o->emptied = malloc(N);
+  o->capped = malloc(N);
   o->f = malloc(sizeof(double) * Q * N);
   o->f2 = malloc(sizeof(double) * Q * N);
   o->m = malloc(sizeof(double) * N);
@@ -639,7 +640,7 @@ fail:
 
 void orc_destroy(orc *o) {
   if (!o) return;
-  void *ptrs[] = {o->type, o->type2, o->filled, o->emptied0, o->emptied, o->f, o->f2, o->m,
+  void *ptrs[] = {o->type, o->type2, o->filled, o->emptied0, o->emptied, o->capped, o->f, o->f2, o->m,
                   o->m2, o->phi, o->phi2, o->rho, o->rho2, o->u, o->u2, o->excess, o->id,
                   o->id2, o->label, o->b_id, o->b_flags, o->b_vstar, o->b_vol, o->b_p,
                   o->b_ncell};
@@ -922,21 +923,29 @@ static int one_step(orc *o) {
    * whatever its fill level (the closed-layer rule of Sec. 2.2 read as in
    * the cited FSLBM of Koerner et al.): without a gas or inlet neighbour
    * it is filled, without a liquid neighbour it is emptied; filling wins
-   * when both hold. */
+   * when both hold.  A cell next to an inlet never fills (the layer around
+   * the inlet stays closed); above 1 + eps it is capped instead: it passes
+   * the mass above m = rho on as excess (phase D) and stays interface, so
+   * that its fill level, the liquid fraction of the cell, stays bounded. */
   for (int64_t i = 0; i < N; ++i) {
     o->filled[i] = 0;
     o->emptied0[i] = 0;
+    o->capped[i] = 0;
     if (o->type[i] != ORC_I) continue;
     int near_in = any_neighbour_type(o, i, ORC_IN);
     int no_gas = !near_in && !any_neighbour_type(o, i, ORC_G);
     int no_liq = !any_neighbour_type(o, i, ORC_L);
     o->filled[i] = (uint8_t)(!near_in && (o->phi2[i] > 1.0 + eps || no_gas));
     o->emptied0[i] = (uint8_t)(o->phi2[i] < -eps || no_liq);
-    if (o->P.freeze_conversions) o->filled[i] = o->emptied0[i] = 0; /* fixed geometry */
+    o->capped[i] = (uint8_t)(near_in && o->phi2[i] > 1.0 + eps);
+    if (o->P.freeze_conversions) /* fixed geometry */
+      o->filled[i] = o->emptied0[i] = o->capped[i] = 0;
   }
   for (int64_t i = 0; i < N; ++i)
     o->emptied[i] = (uint8_t)(o->emptied0[i] && !o->filled[i] &&
                               !any_neighbour_flag(o, i, o->filled));
+  for (int64_t i = 0; i < N; ++i)
+    if (o->emptied[i]) o->capped[i] = 0;
 
   /* Phase C: new types.  Filled -> liquid, emptied -> gas, gas next to a
    * filled cell -> interface, liquid next to an emptied cell -> interface. */
@@ -992,17 +1001,18 @@ static int one_step(orc *o) {
     }
   }
 
-  /* Phase D: excess mass.  A filled cell keeps m = rho and passes on
-   * m - rho; an emptied cell passes on its whole mass.  The excess is split
-   * evenly over the neighbours that are interface cells after the
-   * conversion; without such a neighbour it goes to the bucket. */
+  /* Phase D: excess mass.  A filled (or capped) cell keeps m = rho and
+   * passes on m - rho; an emptied cell passes on its whole mass.  The
+   * excess is split evenly over the neighbours that are interface cells
+   * after the conversion and not capped (a capped cell neither receives
+   * excess nor keeps it); without such a neighbour it goes to the bucket. */
   xsum bucket = {0};
   xsum_add(&bucket, o->bucket); /* carried if there was no interface cell */
   for (int64_t i = 0; i < N; ++i) {
     o->excess[i] = 0.0;
-    if (!(o->filled[i] || o->emptied[i])) continue;
+    if (!(o->filled[i] || o->emptied[i] || o->capped[i])) continue;
     double e;
-    if (o->filled[i]) {
+    if (o->filled[i] || o->capped[i]) {
       e = o->m2[i] - o->rho2[i];
       o->m2[i] = o->rho2[i];
     } else {
@@ -1012,7 +1022,7 @@ static int one_step(orc *o) {
     int nI = 0;
     for (int a = 1; a < Q; ++a) {
       int64_t j = neighbour(o, i, CX[a], CY[a], CZ[a]);
-      if (j >= 0 && o->type2[j] == ORC_I) ++nI;
+      if (j >= 0 && o->type2[j] == ORC_I && !o->capped[j]) ++nI;
     }
     if (nI > 0) o->excess[i] = e / nI;
     else xsum_add(&bucket, e);
@@ -1024,9 +1034,9 @@ static int one_step(orc *o) {
     if (t2 == ORC_I) {
       double add = 0.0;
       int touched = 0;
-      for (int a = 1; a < Q; ++a) {
+      for (int a = 1; a < Q && !o->capped[i]; ++a) {
         int64_t j = neighbour(o, i, CX[a], CY[a], CZ[a]);
-        if (j >= 0 && (o->filled[j] || o->emptied[j])) {
+        if (j >= 0 && (o->filled[j] || o->emptied[j] || o->capped[j])) {
           add += o->excess[j];
           touched = 1;
         }

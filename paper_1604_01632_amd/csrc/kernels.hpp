@@ -752,6 +752,12 @@ __device__ __forceinline__ typename P::R gas_pair(typename P::R rho, typename P:
   }
 }
 
+// Candidate bits of a cell's flag byte after the interface kernel: filled
+// (becomes liquid) and capped (next to an inlet, over-full: stays interface
+// and passes its mass above m = rho on).
+__device__ __forceinline__ bool cand_filled(uint8_t f) { return (f & CAND_F) && !(f & NEAR_INLET); }
+__device__ __forceinline__ bool cand_capped(uint8_t f) { return (f & CAND_F) && (f & NEAR_INLET); }
+
 // Appends the lanes with pred set to a list; returns each such lane's slot.
 // Every lane of the wave must call it.
 __device__ __forceinline__ int wave_append(bool pred, int *counter) {
@@ -995,10 +1001,12 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
   ((R *)d.phi_dst)[i] = phi_new;
   // conversion candidates: fill level beyond the thresholds, or the cell
   // no longer separates liquid from gas (no gas / inlet neighbour: filled;
-  // no liquid neighbour: emptied); never filled next to an inlet
+  // no liquid neighbour: emptied).  A cell next to an inlet is never
+  // filled: there CAND_F means capped (above 1 + eps, it passes the mass
+  // above m = rho on as excess and stays interface)
   uint8_t nf = fl & (STATIC_BITS | TYPE_MASK);
   if (!d.freeze) {
-    if ((phi_new > (R)1 + (R)d.eps || !has_gas) && !(fl & NEAR_INLET)) nf |= CAND_F;
+    if (phi_new > (R)1 + (R)d.eps || (!has_gas && !(fl & NEAR_INLET))) nf |= CAND_F;
     if (phi_new < -(R)d.eps || !has_liq) nf |= CAND_E;
   }
   if (!isfinite(m_new) || !isfinite(rho)) atomicOr(&d.sc->err, ERR_NONFINITE);
@@ -1075,13 +1083,13 @@ struct K_conv_types {
         fdn[a] = d.flag_dst[j];
         fsn[a] = d.flag_src[j];
       }
-      if (fd & CAND_F) {
+      if (cand_filled(fd)) {
         F = true;
       } else if (fd & CAND_E) {
         E = true;
 #pragma unroll
         for (int a = 1; a < Q; ++a)
-          if (fdn[a] & CAND_F) E = false;
+          if (cand_filled(fdn[a])) E = false;
       }
       if (F) d.flag_dst[i] = (uint8_t)((fd & ~TYPE_MASK) | T_LIQ);
       if (E) d.flag_dst[i] = (uint8_t)((fd & ~TYPE_MASK) | T_GAS);
@@ -1336,7 +1344,8 @@ struct K_excess {
     // (every rule below uses them; only the gather tags change in this
     // kernel, so a flag read here stays valid for the type tests)
     const uint8_t t = d.flag_src[i] & TYPE_MASK;
-    const uint8_t tn = d.flag_dst[i] & TYPE_MASK;
+    const uint8_t fdi = d.flag_dst[i];
+    const uint8_t tn = fdi & TYPE_MASK;
     const int slot = d.bslot[i];
     R *mass = (R *)d.mass;
     const R m_i = mass[i], rho_i = ((const R *)d.rhoI)[i];
@@ -1356,26 +1365,33 @@ struct K_excess {
     uint8_t fn[Q];
 #pragma unroll
     for (int a = 1; a < Q; ++a) fn[a] = n1[blk_pos(CX[a], CY[a], CZ[a])];
-    if (t == T_IFACE && (tn == T_LIQ || tn == T_GAS)) {
+    const bool capped = t == T_IFACE && tn == T_IFACE && cand_capped(fdi);
+    if (t == T_IFACE && (tn == T_LIQ || tn == T_GAS || capped)) {
       const bool filled = tn == T_LIQ;
-      const R e = filled ? m_i - rho_i : m_i;
+      const R e = (filled || capped) ? m_i - rho_i : m_i;
+      // receivers: the interface neighbours of t + 1 that are not capped
       int nI = 0;
 #pragma unroll
       for (int a = 1; a < Q; ++a)
-        if ((fn[a] & TYPE_MASK) == T_IFACE) ++nI;
+        if ((fn[a] & TYPE_MASK) == T_IFACE && !cand_capped(fn[a])) ++nI;
       if (nI > 0) {
         ((R *)d.excess)[i] = e / (R)nI;
         // tag the receivers
 #pragma unroll
         for (int a = 1; a < Q; ++a) {
-          if ((fn[a] & TYPE_MASK) == T_IFACE && !(fn[a] & GATHER))
+          if ((fn[a] & TYPE_MASK) == T_IFACE && !cand_capped(fn[a]) && !(fn[a] & GATHER))
             d.flag_dst[nbr(d, x, y, z, CX[a], CY[a], CZ[a])] = (uint8_t)(fn[a] | GATHER);
         }
       } else {
         ((R *)d.excess)[i] = (R)0;
         ex_accumulate(orphan, (double)e);
       }
-      if (filled) {
+      if (capped) {
+        // stays an interface cell with m = rho (its fill level 1 plus what
+        // it gathers from converted neighbours)
+        mass[i] = rho_i;
+        ((R *)d.phi_dst)[i] = (R)1;
+      } else if (filled) {
         mass[i] = rho_i;
         ((R *)d.phi_src)[i] = (R)1;
         ((R *)d.phi_dst)[i] = (R)1;
@@ -1458,8 +1474,10 @@ struct K_gather {
           for (int a = 1; a < Q; ++a) {
             const long long j = nb.at(d, CX[a], CY[a], CZ[a]);
             const uint8_t t0 = d.flag_src[j] & TYPE_MASK;
-            const uint8_t t1 = d.flag_dst[j] & TYPE_MASK;
-            conv[a] = t0 == T_IFACE && (t1 == T_LIQ || t1 == T_GAS);
+            const uint8_t f1 = d.flag_dst[j];
+            const uint8_t t1 = f1 & TYPE_MASK;
+            conv[a] = t0 == T_IFACE && (t1 == T_LIQ || t1 == T_GAS ||
+                                        (t1 == T_IFACE && cand_capped(f1)));
             ex[a] = ((const R *)d.excess)[j];
           }
 #pragma unroll

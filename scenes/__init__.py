@@ -394,6 +394,11 @@ def config(name: str) -> Scene:
     c3     128x128x256 walled box, inlet disk r = 6 in the bottom wall,
            Q = 0.05 per step, g = 1e-5 in -z, tau 0.6, sigma 2e-3
            (bubble detachment, Sec. 3.2 stand-in).
+    c3d    48x48x96 walled box, inlet disk r = 3, Q = 0.05, g = 4e-4,
+           tau 0.6, sigma 2e-3: a detaching variant of c3 (with c3's own
+           parameters the first bubble would detach only after ~150 000
+           steps); bubbles pinch off at ~2600 and ~5500 steps, rise and
+           coalesce (~9000).
     p1     256^3 periodic, 16 gas threads of the c2 geometry on a 4x4 grid
            (x, y in {32, 96, 160, 224}), seed 256.
     p0     256^3 all liquid (bulk ceiling).
@@ -404,6 +409,8 @@ def config(name: str) -> Scene:
         return threads(name="c2")
     if name == "c3":
         return orifice(name="c3")
+    if name == "c3d":
+        return orifice(n=(48, 48, 96), r=3.0, g=4e-4, Q=0.05, steps=12000, name="c3d")
     if name == "p1":
         return thread_lattice(n=(256, 256, 256), spacing=64, seed=256, steps=4000, name="p1")
     if name == "p0":

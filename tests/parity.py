@@ -213,3 +213,32 @@ def compare_fp32_step(do, bo, so, dg, bg, sg, N, eps, audit):
         assert v <= TOL_BUBBLE
     assert merr <= TOL_MASS32
     assert so["step"] == sg["step"] and so["next_id"] == sg["next_id"]
+
+
+# Bubbles of two runs whose ID sequences differ (the forms see slightly
+# different numbers of topology events) are paired by position.
+def centroids(bid, ids, shape):
+    """Centroid of every bubble's cells in the periodic box (circular mean
+    per axis), in cell units."""
+    nz, ny, nx = shape
+    sel = bid >= 0
+    cells = np.nonzero(sel)[0]
+    lab = np.searchsorted(ids, bid[sel])
+    out = np.zeros((len(ids), 3))
+    for k, (n, coord) in enumerate(((nx, cells % nx), (ny, (cells // nx) % ny),
+                                    (nz, cells // (nx * ny)))):
+        a = 2 * np.pi * coord / n
+        c = np.bincount(lab, np.cos(a), len(ids))
+        s_ = np.bincount(lab, np.sin(a), len(ids))
+        out[:, k] = (np.arctan2(s_, c) % (2 * np.pi)) * n / (2 * np.pi)
+    return out
+
+
+def match_by_centroid(ca, cb, shape):
+    """For every bubble of a, the nearest bubble of b (periodic distance);
+    None unless that is one to one."""
+    L = np.array([shape[2], shape[1], shape[0]], float)
+    d = np.abs(ca[:, None, :] - cb[None, :, :])
+    d = np.minimum(d, L - d)
+    m = np.argmin(np.sqrt((d ** 2).sum(-1)), axis=1)
+    return m if len(set(m.tolist())) == len(m) else None

@@ -14,12 +14,15 @@ import pytest
 
 import scenes
 from scenes import GAS, IFACE, INLET, LIQ
-from tests.parity import compare_fp32_step, compare_state, near_tie, oracle_from_state, say
+from tests.parity import (centroids as _centroids, compare_fp32_step, compare_state,
+                          match_by_centroid as _match_by_centroid, near_tie, oracle_from_state,
+                          say)
 
 pytestmark = pytest.mark.gpu
 
-WARMUP = 1000        # untimed steps of the benchmark before its window
-PHASE_PERIOD = 25    # the benchmark's phase-timing period in the window
+WARMUP = 1125        # untimed steps of the benchmark before its window (1120 + 5)
+PHASE_PERIOD = 8     # the benchmark's timing period in its 80-step window
+PHASE_MASK = ["bulk"]  # the benchmark times the stream-collide kernel only
 HORIZON = 4000
 
 
@@ -71,7 +74,7 @@ def _advance(d, to_step: int) -> None:
         d.step(n)
         s += n
     if s >= WARMUP:
-        F.fslbm_set_timing(d.handle, PHASE_PERIOD)
+        F.fslbm_set_timing(d.handle, PHASE_PERIOD, PHASE_MASK)
         if to_step > s:
             d.step(to_step - s)
     d.sync()
@@ -178,33 +181,6 @@ def _closed_layer_and_ids(t, bid, live, shape):
     assert np.all(bid[~inset] == -1)
 
 
-def _centroids(bid, ids, shape):
-    """Centroid of every bubble's cells in the periodic box (circular mean
-    per axis), in cell units."""
-    nz, ny, nx = shape
-    sel = bid >= 0
-    cells = np.nonzero(sel)[0]
-    lab = np.searchsorted(ids, bid[sel])
-    out = np.zeros((len(ids), 3))
-    for k, (n, coord) in enumerate(((nx, cells % nx), (ny, (cells // nx) % ny),
-                                    (nz, cells // (nx * ny)))):
-        a = 2 * np.pi * coord / n
-        c = np.bincount(lab, np.cos(a), len(ids))
-        s_ = np.bincount(lab, np.sin(a), len(ids))
-        out[:, k] = (np.arctan2(s_, c) % (2 * np.pi)) * n / (2 * np.pi)
-    return out
-
-
-def _match_by_centroid(ca, cb, shape):
-    """For every bubble of a, the nearest bubble of b (periodic distance);
-    None unless that is one to one."""
-    L = np.array([shape[2], shape[1], shape[0]], float)
-    d = np.abs(ca[:, None, :] - cb[None, :, :])
-    d = np.minimum(d, L - d)
-    m = np.argmin(np.sqrt((d ** 2).sum(-1)), axis=1)
-    return m if len(set(m.tolist())) == len(m) else None
-
-
 def _horizon(p1, prec):
     """Run the scene to its horizon in one form: bubbles, mass drift,
     topology changes and bubble centroids; the reduced forms also get the
@@ -261,7 +237,13 @@ def test_p1_reduced_precision_against_fp64_over_horizon(p1, p1_fp64_horizon, pre
     and a live bubble ID on every gas-region cell, and volumes within 1e-3
     relative.  The FP16-deviation form misses the volume bound on one large
     bubble at this horizon (1.1e-3); that case is reported as an expected
-    failure with its number, after the other bounds have been asserted."""
+    failure with its number, after the other bounds have been asserted.
+    The error is not a drift: it is 1.05e-3 at step 1200, right after the
+    rupture, and stays between 1.05e-3 and 1.14e-3 up to step 4000; the
+    FP16 run sees 46 merges and splits where FP64 sees 48, so a neck closed
+    at another moment and the gas amount V* was divided between the
+    daughters in other proportions (the split keeps each daughter's share
+    of the mother's V* at the moment of the split)."""
     ref, _, _, rcent = p1_fp64_horizon
     b, drift, _, cent = _horizon(p1, prec)
     assert len(b["id"]) == len(ref["id"]) > 16
@@ -270,5 +252,6 @@ def test_p1_reduced_precision_against_fp64_over_horizon(p1, p1_fp64_horizon, pre
     say(f"[fullsize] p1 {prec}: bubbles {len(b['id'])} (fp64 {len(ref['id'])}), "
         f"max volume error {vol:.2e} (bubble of volume {at:.1f}), drift {drift:.2e}")
     if prec == "fp16dev" and vol > 1e-3:
-        pytest.xfail(f"FP16-deviation volume error {vol:.2e} > 1e-3 at the 256^3 horizon")
+        pytest.xfail(f"FP16-deviation volume error {vol:.2e} > 1e-3 at the 256^3 horizon, set at "
+                     "the rupture by a differently timed pinch-off (not a drift)")
     assert vol <= 1e-3

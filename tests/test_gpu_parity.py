@@ -91,6 +91,22 @@ def test_orifice_injection():
     run_pair(sc, 40, 10, "orifice")
 
 
+def test_orifice_rim_capping():
+    """An under-pressured inlet bubble pulls liquid over the orifice: the
+    interface cells next to the inlet go over-full and are capped (they
+    keep m = rho and pass the rest on) every step; bitwise against the
+    oracle."""
+    sc = scenes.orifice(n=(16, 16, 20), r=3.0, g=1e-5, Q=0.0)
+    sc.bubbles = [(b[0], b[1], b[2], b[3] * 0.8) for b in sc.bubbles]
+    nx, ny = sc.nx, sc.ny
+    z = np.arange(sc.n) // (nx * ny)
+    above = np.roll(sc.cell_type == scenes.INLET, nx * ny) & (z == 1)
+    sc.phi = np.where(above, 0.999, sc.phi)
+    o, g = run_pair(sc, 30, 5, "orifice-capping")
+    d = o.read()
+    assert np.any(d["phi"][above] == 1.0)  # capped cells in the final state
+
+
 def test_flat_interface_and_all_liquid_edge_cases():
     """Degenerate scenes: a flat interface sliding in a periodic box, an
     all-liquid box, a one-cell-wide line and an all-gas box."""
@@ -224,34 +240,6 @@ def test_sampled_phase_timing_leaves_results_unchanged():
     ra, rb = a.read(), b.read()
     for key in ("cell_type", "bubble_id", "phi", "mass", "f"):
         assert np.array_equal(ra[key], rb[key]), key
-
-
-def test_reduced_precision_at_thread_rupture_horizon():
-    """FP32 and FP16-deviation storage against the FP64 form over the whole
-    thread-rupture horizon (64x64x256, 20000 steps, several breakups): the
-    same bubble count, volumes within 1e-3 relative and total-mass drift at
-    most 1e-6 relative.  The FP64 form reproduces the oracle bit for bit on
-    the parity cases; at this horizon it stands in for the oracle."""
-    from paper_1604_01632_amd import Domain
-    sc = scenes.config("c2")
-    out = {}
-    for prec in ("fp64", "fp32", "fp16dev"):
-        d = Domain.from_scene(sc, prec)
-        m0 = d.read(("cell_type",))["scalars"]["total_mass"]
-        for _ in range(4):
-            d.step(5000)
-            d.sync()
-        s = d.read(("cell_type",))["scalars"]
-        out[prec] = (d.bubbles(), abs(s["total_mass"] - m0) / m0)
-        d.close()
-    ref = out["fp64"][0]
-    for prec in ("fp32", "fp16dev"):
-        b, drift = out[prec]
-        say(f"[horizon] c2 {prec}: {len(b['id'])} bubbles (fp64 {len(ref['id'])}), volumes "
-            f"{np.sort(b['volume'])} vs {np.sort(ref['volume'])}, mass drift {drift:.2e}")
-        assert len(b["id"]) == len(ref["id"]) >= 2
-        assert np.allclose(np.sort(b["volume"]), np.sort(ref["volume"]), rtol=1e-3)
-        assert drift <= 1e-6
 
 
 def test_fp32_step_with_walls_matches_oracle():
