@@ -59,7 +59,7 @@ enum {
   FSLBM_ENUMERIC = -4,  /* non-finite density, mass or fill level; a broken
                            interface layer or mass drift found by the
                            watchdog; an internal list overflow */
-  FSLBM_ECAPACITY = -5  /* bubble table full */
+  FSLBM_ECAPACITY = -5  /* bubble table or interface list full */
 };
 
 /* Cell types (Sec. 2.2, Fig. 1, plus walls and gas inlets of Sec. 3.2). */
@@ -114,6 +114,11 @@ typedef struct {
   double trigger_cos;     /* FSLBM_TRIGGER_NORMALS: two unit normals are
                              anti-parallel when their dot product is below
                              this value (e.g. -0.5) */
+  int32_t iface_capacity; /* interface cells the per-slot arrays of the
+                             interface list hold (0: min(N, max(N/6,
+                             65536))); more interface cells in a step is
+                             FSLBM_ECAPACITY */
+  int32_t pad_;
 } fslbm_params;
 
 /* What starts the connected-component labelling of a bubble (Sec. 2.3).

@@ -67,8 +67,16 @@ struct Layout {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Interface cells the list and its per-slot arrays hold.
+long long iface_capacity(const fslbm_params &p) {
+  const long long N = (long long)p.nx * p.ny * p.nz;
+  if (p.iface_capacity > 0) return std::min<long long>(p.iface_capacity, N);
+  return std::min<long long>(N, std::max<long long>(N / 6, 65536));
+}
+
 Layout make_layout(const fslbm_params &p, const Launchers &L) {
   const size_t N = (size_t)p.nx * p.ny * p.nz;
+  const size_t C = (size_t)iface_capacity(p);
   const size_t B = (size_t)p.max_bubbles;
   size_t sz[A_COUNT];
   sz[A_F0] = sz[A_F1] = (size_t)Q * N * L.store_bytes;
@@ -83,14 +91,15 @@ Layout make_layout(const fslbm_params &p, const Launchers &L) {
   sz[A_SCALARS] = sizeof(Scalars);
   sz[A_MASSACC] = SUB_MASS * 2 * 8;
   sz[A_BUCKETACC] = SUB * EX_WORDS * 8;
-  sz[A_ILIST0] = sz[A_ILIST1] = sz[A_CLIST] = sz[A_NLIST] = N * 4;
+  sz[A_ILIST0] = sz[A_ILIST1] = C * 4;
+  sz[A_CLIST] = sz[A_NLIST] = N * 4;
   sz[A_MARK] = ((N + 3) / 4) * 4;
-  sz[A_GASV] = N * L.real_bytes;
-  sz[A_NMASK] = N * 4;
-  sz[A_NRM] = p.split_trigger == FSLBM_TRIGGER_NORMALS ? 3 * N * 4 : 0;
+  sz[A_GASV] = C * L.real_bytes;
+  sz[A_NMASK] = C * 4;
+  sz[A_NRM] = p.split_trigger == FSLBM_TRIGGER_NORMALS ? 3 * C * 4 : 0;
   sz[A_TILECOUNT] = sz[A_TILEOFF] = ((N + 4095) / 4096) * 4;
-  sz[A_FIF0] = sz[A_FIF1] = N * (((size_t)Q * L.store_bytes + 15) / 16 * 16);  // one padded row per slot
-  sz[A_NFLAG] = N;
+  sz[A_FIF0] = sz[A_FIF1] = C * (((size_t)Q * L.store_bytes + 15) / 16 * 16);  // one padded row per slot
+  sz[A_NFLAG] = C;
   sz[A_ISLOT0] = sz[A_ISLOT1] = N * 4;
   Layout lay;
   size_t o = 0;
@@ -122,6 +131,7 @@ const char *check_params(const fslbm_params *p) {
     return "freeze_conversions must be 0 or 1";
   if (p->watchdog_every < 0) return "watchdog_every must be >= 0";
   if (p->debug_flags & ~FSLBM_DEBUG_NO_LAYER_CHECK) return "unknown debug_flags bits";
+  if (p->iface_capacity < 0) return "iface_capacity must be >= 0";
   if (p->split_trigger != FSLBM_TRIGGER_EXACT && p->split_trigger != FSLBM_TRIGGER_NORMALS)
     return "unknown split_trigger";
   if (p->split_trigger == FSLBM_TRIGGER_NORMALS && !(p->trigger_cos >= -1.0 && p->trigger_cos <= 1.0))
@@ -172,6 +182,7 @@ void build_devs(Ctx &c) {
   d.force_topology = c.P.force_topology;
   d.freeze = c.P.freeze_conversions;
   d.split_trigger = c.P.split_trigger;
+  d.icap = (int)iface_capacity(c.P);
   d.trigger_cos = c.P.trigger_cos;
   d.drift_tol = c.P.watchdog_drift;
   d.collision = c.P.collision;
@@ -475,6 +486,9 @@ int sync_and_check(Ctx &c) {
   if (sc.err & ERR_NONFINITE)
     return fail(FSLBM_ENUMERIC, "non-finite density, mass or fill level (or total mass)");
   if (sc.err & ERR_RANGE) return fail(FSLBM_ENUMERIC, "conversion candidate list overflow");
+  if (sc.err & ERR_ILIST)
+    return fail(FSLBM_ECAPACITY, "interface list full: more interface cells than iface_capacity (" +
+                                     std::to_string(iface_capacity(c.P)) + ")");
   if (sc.err & ERR_LAYER)
     return fail(FSLBM_ENUMERIC, "watchdog: a liquid cell touches a gas or inlet cell "
                                 "(the interface layer is not closed)");
@@ -684,6 +698,10 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
       mass_h[i] = 0.0;
     }
   }
+  if (n_iface > iface_capacity(p))
+    return fail(FSLBM_ECAPACITY, "the initial state has " + std::to_string(n_iface) +
+                                     " interface cells, more than iface_capacity (" +
+                                     std::to_string(iface_capacity(p)) + ")");
 
   Ctx *c = new Ctx();
   c->P = p;

@@ -89,6 +89,7 @@ constexpr int ERR_RANGE = 4;
 constexpr int ERR_LAYER = 8;    // a liquid cell next to a gas or inlet cell
 constexpr int ERR_ORPHAN = 16;  // a gas-region cell without a live bubble
 constexpr int ERR_DRIFT = 32;   // total mass drifted beyond the watchdog bound
+constexpr int ERR_ILIST = 64;   // more interface cells than the list capacity
 
 // Everything a kernel needs, passed by value.  src/dst refer to time t and
 // t+1 of the current step.
@@ -100,6 +101,7 @@ struct Dev {
   int force_topology;
   int freeze;     // no conversions (cell types stay fixed)
   int split_trigger;  // 0 exact 3x3x3 test, 1 anti-parallel normals
+  int icap;           // capacity of the interface list and its per-slot arrays
   double trigger_cos;
   int collision;
   double drift_tol;  // watchdog: relative total-mass drift bound (<= 0: off)
@@ -133,7 +135,7 @@ struct Dev {
   // trigger by normals only)
   void *gasv;
   uint32_t *nmask;
-  float *nrm;  // [3][N] by slot of the list of t
+  float *nrm;  // [3][icap] by slot of the list of t
   // per tile of the ordered interface-list build: counts and offsets
   int32_t *tilecount, *tileoff;
   // outputs of the interface kernel by list slot (post-collision values,

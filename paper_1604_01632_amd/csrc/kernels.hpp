@@ -720,10 +720,10 @@ struct K_geom {
       // unit normal for the split trigger by anti-parallel normals
       const float len = (float)sqrt((double)(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]));
       const float inv = len > 0.0f ? 1.0f / len : 0.0f;
-      const long long N = d.N;
+      const long long C = d.icap;
       d.nrm[k] = (float)nv[0] * inv;
-      d.nrm[N + k] = (float)nv[1] * inv;
-      d.nrm[2 * N + k] = (float)nv[2] * inv;
+      d.nrm[C + k] = (float)nv[1] * inv;
+      d.nrm[2 * C + k] = (float)nv[2] * inv;
     }
   }
 }
@@ -1304,7 +1304,7 @@ __device__ __forceinline__ bool antiparallel_normals(const Dev &d, int x, int y,
                                                      const uint8_t (&n0)[27]) {
   float nx[18], ny[18], nz[18];
   int cnt = 0;
-  const long long N = d.N;
+  const long long C = d.icap;
 #pragma unroll
   for (int p = 0; p < 27; ++p) {
     const int dx = p % 3 - 1, dy = (p / 3) % 3 - 1, dz = p / 9 - 1;
@@ -1315,8 +1315,8 @@ __device__ __forceinline__ bool antiparallel_normals(const Dev &d, int x, int y,
     if (d.bslot[j] != slot) continue;
     const int k = d.islot[j];
     nx[cnt] = d.nrm[k];
-    ny[cnt] = d.nrm[N + k];
-    nz[cnt] = d.nrm[2 * N + k];
+    ny[cnt] = d.nrm[C + k];
+    nz[cnt] = d.nrm[2 * C + k];
     ++cnt;
   }
   const float c = (float)d.trigger_cos;
@@ -1585,7 +1585,12 @@ struct K_list_scan {
     d.tileoff[k] = run;
     run += c;
   }
-  if (threadIdx.x == blockDim.x - 1) d.sc->n_il_dst = sums[threadIdx.x];
+  if (threadIdx.x == blockDim.x - 1) {
+    // beyond the capacity the list is cut (an error the host reports)
+    const int total = sums[threadIdx.x];
+    if (total > d.icap) atomicOr(&d.sc->err, ERR_ILIST);
+    d.sc->n_il_dst = total < d.icap ? total : d.icap;
+  }
 }
 };
 
@@ -1614,8 +1619,10 @@ struct K_list_fill {
   for (int b = 0; b < 16; ++b) {
     if ((bits >> b) & 1u) {
       const long long i = i0 + b;
-      d.ilist_dst[pos] = (int)i;
-      d.islot_alt[i] = pos;  // the slots of the next step
+      if (pos < d.icap) {
+        d.ilist_dst[pos] = (int)i;
+        d.islot_alt[i] = pos;  // the slots of the next step
+      }
       ++pos;
     }
   }

@@ -62,7 +62,7 @@ class Scene:
             trt_lambda=3.0 / 16.0, sigma=self.sigma, g=tuple(self.g), p0=P0,
             eps_convert=self.eps, inject_rate=self.inject_rate,
             max_bubbles=1024, force_topology=0, freeze_conversions=0, watchdog_every=0,
-            watchdog_drift=0.0, debug_flags=0, split_trigger=0, trigger_cos=-0.5,
+            watchdog_drift=0.0, debug_flags=0, split_trigger=0, trigger_cos=-0.5, iface_capacity=0,
         )
         d.update(over)
         return d

@@ -184,3 +184,37 @@ def test_copy_bandwidth_probe():
     gbs = fslbm_copy_bandwidth(dst, src, 3)
     assert torch.equal(src, dst)
     assert 10.0 < gbs < 20000.0
+
+
+def test_interface_list_capacity():
+    """The per-slot arrays of the interface list hold iface_capacity cells:
+    an initial state with more interface cells is refused, and a run whose
+    interface grows past the capacity reports FSLBM_ECAPACITY (the list is
+    cut, nothing is written beyond it)."""
+    from paper_1604_01632_amd import Domain, FslbmError, FSLBM_ECAPACITY
+    # an over-pressured bubble expands: its interface grows
+    sc = scenes.spheres(n=(24, 24, 24), centers=((12.0, 12.0, 12.0),), radii=(5.0,),
+                        p_init=(1.3 * P0,), rho_l=1.0, sigma=1e-3)
+    n0 = int(np.count_nonzero(sc.cell_type == IFACE))
+    with pytest.raises(FslbmError) as e:
+        Domain.from_scene(sc, "fp32", iface_capacity=n0 - 1)
+    assert e.value.code == FSLBM_ECAPACITY
+    ref = Domain.from_scene(sc, "fp32")
+    counts = []
+    for _ in range(40):
+        ref.step(1)
+        counts.append(int(np.count_nonzero(ref.read(("cell_type",))["cell_type"] == IFACE)))
+    # room for the start but not for the largest list of the run
+    cap = max(n0, max(counts) - 1)
+    assert max(counts) > cap >= n0
+    d = Domain.from_scene(sc, "fp32", iface_capacity=cap)
+    d.step(40)
+    with pytest.raises(FslbmError) as e:
+        d.sync()
+    assert e.value.code == FSLBM_ECAPACITY and "interface list" in str(e.value)
+    # with room for all of them the run is the default one
+    ok = Domain.from_scene(sc, "fp32", iface_capacity=max(counts))
+    ok.step(40)
+    ra, rb = ok.read(), ref.read()
+    for key in ("cell_type", "bubble_id", "phi", "mass", "f"):
+        assert np.array_equal(ra[key], rb[key]), key
