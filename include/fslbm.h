@@ -343,6 +343,17 @@ int fslbm_batch_create_noalloc(void *const *handles, int32_t n, void *stream, vo
  * fslbm_read_fields or fslbm_bubbles on its handle. */
 int fslbm_batch_step(void *batch, int32_t n_steps);
 
+/* Replace the members of a batch by handles[n] (same precision; n at most
+ * the domains its table space holds: the workspace size given at creation,
+ * see fslbm_batch_workspace_bytes).  Domains may come and go this way, as
+ * in a serving loop, without creating a new batch: the tables are
+ * rewritten in place, ordered on the batch's stream after the steps already
+ * queued (no wait for them), and from the first reset on the batch's steps
+ * are plain kernel launches instead of graph replays (its graphs are
+ * dropped; the kernels and results are the same).  A batch of
+ * fslbm_batch_create_noalloc keeps its rule: every domain on its stream. */
+int fslbm_batch_reset(void *batch, void *const *handles, int32_t n);
+
 /* The autotuning outcome of the batch. */
 int fslbm_batch_info_get(void *batch, fslbm_batch_info *out);
 

@@ -115,6 +115,8 @@ def lib() -> C.CDLL:
         L.fslbm_batch_create_noalloc.restype = C.c_int
         L.fslbm_batch_create_noalloc.argtypes = [C.POINTER(C.c_void_p), C.c_int32, P,
                                                  C.POINTER(C.c_void_p)]
+        L.fslbm_batch_reset.restype = C.c_int
+        L.fslbm_batch_reset.argtypes = [P, C.POINTER(C.c_void_p), C.c_int32]
         L.fslbm_batch_step.restype = C.c_int
         L.fslbm_batch_step.argtypes = [P, C.c_int32]
         L.fslbm_batch_info_get.restype = C.c_int
@@ -291,9 +293,9 @@ class Domain:
                                    self.workspace, stream, f_init, restore, mass_init)
 
     @classmethod
-    def from_scene(cls, sc, precision="fp64", **over):
+    def from_scene(cls, sc, precision="fp64", stream=None, **over):
         return cls(sc.params(precision=PRECISIONS[precision] if isinstance(precision, str) else precision, **over),
-                   sc.cell_type, sc.phi, sc.rho, sc.u, sc.bubble_id, sc.bubbles)
+                   sc.cell_type, sc.phi, sc.rho, sc.u, sc.bubble_id, sc.bubbles, stream=stream)
 
     def step(self, n: int = 1) -> None:
         fslbm_step(self.handle, n)
@@ -355,6 +357,11 @@ def fslbm_batch_step(batch, n_steps: int) -> None:
     _check(lib().fslbm_batch_step(batch, int(n_steps)))
 
 
+def fslbm_batch_reset(batch, handles) -> None:
+    arr = (C.c_void_p * len(handles))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    _check(lib().fslbm_batch_reset(batch, arr, len(handles)))
+
+
 def fslbm_batch_info_get(batch) -> dict:
     info = BatchInfo()
     _check(lib().fslbm_batch_info_get(batch, C.byref(info)))
@@ -367,19 +374,26 @@ def fslbm_batch_destroy(batch) -> None:
 
 
 class Batch:
-    """Many domains advanced together (one graph launch per step)."""
+    """Many domains advanced together (one graph launch per step).
+    capacity: domains the batch may hold after a reset (default: the given
+    ones)."""
 
-    def __init__(self, domains, tuning_cache_path=None, stream=None):
+    def __init__(self, domains, tuning_cache_path=None, stream=None, capacity=None):
         import torch
 
         self.domains = list(domains)
-        nbytes = fslbm_batch_workspace_bytes(len(self.domains))
+        nbytes = fslbm_batch_workspace_bytes(max(len(self.domains), capacity or 0))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.domains[0].workspace.device)
         self.handle = fslbm_batch_create([d.handle for d in self.domains], tuning_cache_path,
                                          self.workspace, stream)
 
     def step(self, n: int = 1) -> None:
         fslbm_batch_step(self.handle, n)
+
+    def reset(self, domains) -> None:
+        """Replace the members (the batch then steps with plain launches)."""
+        fslbm_batch_reset(self.handle, [d.handle for d in domains])
+        self.domains = list(domains)
 
     def info(self) -> dict:
         return fslbm_batch_info_get(self.handle)

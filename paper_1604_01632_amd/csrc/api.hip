@@ -305,17 +305,43 @@ struct Batch {
   // tables in the library's static scratch array: no own stream, events or
   // graphs; steps are plain launches on the caller's stream
   bool in_scratch = false;
+  // steps as plain launches instead of graph replays (after a reset)
+  bool direct = false;
+  int cap = 0;  // domains the table space holds (fixed table offsets)
+  // pinned host staging of the tables, two buffers used in turn, each
+  // reusable once the copy out of it (event) has completed
+  char *stage[2] = {nullptr, nullptr};
+  hipEvent_t stage_ev[2] = {nullptr, nullptr};
+  int stage_cur = 0;
 };
 
 size_t batch_bytes(int nd) {
   return align256(2 * (size_t)nd * sizeof(Dev)) + G_COUNT * align256((size_t)(nd + 1) * 4);
 }
 
+// Domains a table space of `bytes` holds.
+int batch_capacity(size_t bytes) {
+  int lo = 0, hi = 1 << 24;
+  while (hi - lo > 1) {
+    const int mid = lo + (hi - lo) / 2;
+    if (batch_bytes(mid) <= bytes) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Device tables for the current domain order and parities: the Dev of
 // every domain for the next step (relative parity 0) and the one after
 // (1), and per grid class the first block of every domain.
+// Tables at fixed offsets for the batch's capacity (the kernel arguments
+// that point at them stay valid when the members change): the Devs of the
+// two parities, then per grid class the block offsets.  Written through the
+// pinned staging buffers without waiting for the stream, or, for a batch in
+// the scratch array (which allocates nothing, not even pinned host memory),
+// from pageable memory with a wait.
 int batch_tables(Batch &b, int bulk_threads) {
   const int nd = (int)b.dom.size();
+  const int cap = b.cap > 0 ? b.cap : nd;
   std::vector<Dev> devs(2 * (size_t)nd);
   std::vector<int> off[G_COUNT];
   for (int g = 0; g < G_COUNT; ++g) off[g].assign(nd + 1, 0);
@@ -328,17 +354,36 @@ int batch_tables(Batch &b, int bulk_threads) {
     const LaunchCfg lc = make_cfg(c.P, bulk_threads);
     for (int g = 0; g < G_COUNT; ++g) off[g][k + 1] = off[g][k] + lc.blocks[g];
   }
+  // the image of the table space: [Dev x cap][Dev x cap] then per class
+  // (cap + 1) offsets, each part 256-byte aligned
+  const size_t dev_part = align256(2 * (size_t)cap * sizeof(Dev));
+  const size_t off_part = align256((size_t)(cap + 1) * 4);
+  const size_t total = dev_part + G_COUNT * off_part;
+  std::vector<char> pageable;
+  char *img;
+  if (b.stage[0]) {
+    const int k = b.stage_cur;
+    HIP_TRY(hipEventSynchronize(b.stage_ev[k]));  // its previous copy is done
+    img = b.stage[k];
+  } else {
+    pageable.resize(total);
+    img = pageable.data();
+  }
+  std::memcpy(img, devs.data(), (size_t)nd * sizeof(Dev));
+  std::memcpy(img + (size_t)cap * sizeof(Dev), devs.data() + nd, (size_t)nd * sizeof(Dev));
+  for (int g = 0; g < G_COUNT; ++g)
+    std::memcpy(img + dev_part + g * off_part, off[g].data(), (size_t)(nd + 1) * 4);
   char *p = b.ws;
   b.d_devs[0] = (Dev *)p;
-  b.d_devs[1] = (Dev *)p + nd;
-  HIP_TRY(hipMemcpyAsync(p, devs.data(), devs.size() * sizeof(Dev), hipMemcpyHostToDevice, b.stream));
-  p += align256(2 * (size_t)nd * sizeof(Dev));
-  for (int g = 0; g < G_COUNT; ++g) {
-    b.d_off[g] = (int *)p;
-    HIP_TRY(hipMemcpyAsync(p, off[g].data(), (nd + 1) * 4, hipMemcpyHostToDevice, b.stream));
-    p += align256((size_t)(nd + 1) * 4);
+  b.d_devs[1] = (Dev *)p + cap;
+  for (int g = 0; g < G_COUNT; ++g) b.d_off[g] = (int *)(p + dev_part + g * off_part);
+  HIP_TRY(hipMemcpyAsync(p, img, total, hipMemcpyHostToDevice, b.stream));
+  if (b.stage[0]) {
+    HIP_TRY(hipEventRecord(b.stage_ev[b.stage_cur], b.stream));
+    b.stage_cur ^= 1;
+  } else {
+    HIP_TRY(hipStreamSynchronize(b.stream));
   }
-  HIP_TRY(hipStreamSynchronize(b.stream));
   for (int r = 0; r < 2; ++r) {
     BatchCfg &bc = b.cfg[r];
     bc.devs = b.d_devs[r];
@@ -472,6 +517,10 @@ void batch_free(Batch *b) {
   }
   if (b->stream) hipStreamSynchronize(b->stream);
   batch_drop_graphs(*b);
+  for (int k = 0; k < 2; ++k) {
+    if (b->stage_ev[k]) hipEventDestroy(b->stage_ev[k]);
+    if (b->stage[k]) hipHostFree(b->stage[k]);
+  }
   if (b->ev_in) hipEventDestroy(b->ev_in);
   if (b->ev_out) hipEventDestroy(b->ev_out);
   if (b->stream) hipStreamDestroy(b->stream);
@@ -1034,6 +1083,7 @@ int fslbm_batch_create(void *const *handles, int32_t n, const char *tuning_cache
   b->L = given[0]->L;
   b->user_stream = (hipStream_t)stream;
   b->ws = (char *)device_workspace;
+  b->cap = batch_capacity(workspace_bytes);
   auto bail = [&](int code) {
     std::string msg = g_err;
     batch_free(b);
@@ -1045,6 +1095,18 @@ int fslbm_batch_create(void *const *handles, int32_t n, const char *tuning_cache
       hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
     fail(FSLBM_EDEVICE, "batch: stream or event creation failed");
     return bail(FSLBM_EDEVICE);
+  }
+  for (int k = 0; k < 2; ++k) {
+    if (hipHostMalloc((void **)&b->stage[k], batch_bytes(b->cap), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->stage_ev[k], hipEventDisableTiming) != hipSuccess) {
+      fail(FSLBM_EDEVICE, "batch: pinned staging or event creation failed");
+      return bail(FSLBM_EDEVICE);
+    }
+    // a recorded event that has completed: the buffer is free
+    if (hipEventRecord(b->stage_ev[k], b->stream) != hipSuccess) {
+      fail(FSLBM_EDEVICE, "batch: event record failed");
+      return bail(FSLBM_EDEVICE);
+    }
   }
   // finish whatever the domains' own streams hold (creation uploads)
   for (Ctx *c : given)
@@ -1087,6 +1149,10 @@ int fslbm_batch_create(void *const *handles, int32_t n, const char *tuning_cache
   batch_order(*b, given, order);
   int rc = batch_tables(*b, threads);
   if (rc == FSLBM_OK) rc = batch_capture(*b);
+  if (rc == FSLBM_OK && hipStreamSynchronize(b->stream) != hipSuccess) {
+    fail(FSLBM_EDEVICE, "batch: table upload failed");
+    rc = FSLBM_EDEVICE;
+  }
   if (rc != FSLBM_OK) return bail(rc);
   *out_batch = b;
   g_err.clear();
@@ -1126,6 +1192,7 @@ int fslbm_batch_create_noalloc(void *const *handles, int32_t n, void *stream, vo
   for (Ctx *c : given) cells += c->N;
   b->info.cells = cells;
   b->info.bulk_threads = 256;
+  b->cap = batch_capacity(SCRATCH_BYTES);
   int rc = batch_tables(*b, 256);
   if (rc != FSLBM_OK) {
     delete b;
@@ -1150,7 +1217,7 @@ int fslbm_batch_step(void *batch, int32_t n_steps) {
   int r = r0;
   if (!same) {
     int rc = batch_tables(b, b.info.bulk_threads);
-    if (rc == FSLBM_OK && !b.in_scratch) rc = batch_capture(b);
+    if (rc == FSLBM_OK && !b.in_scratch && !b.direct) rc = batch_capture(b);
     if (rc != FSLBM_OK) return rc;
     r = 0;
   }
@@ -1170,7 +1237,7 @@ int fslbm_batch_step(void *batch, int32_t n_steps) {
   int rc = FSLBM_OK;
   int done = 0;
   for (int s = 0; s < n_steps && rc == FSLBM_OK; ++s) {
-    if (b.in_scratch) {
+    if (b.in_scratch || b.direct) {
       for (int ph = 0; ph < PH_COUNT; ++ph) b.L.batch_phase(ph, b.cfg[(r + s) & 1], b.stream);
     } else {
       HIP_TRY(hipGraphLaunch(b.exec[(r + s) & 1], b.stream));
@@ -1208,6 +1275,34 @@ int fslbm_batch_step(void *batch, int32_t n_steps) {
   }
   for (Ctx *c : b.dom) c->cur ^= (done & 1);
   return rc;
+}
+
+int fslbm_batch_reset(void *batch, void *const *handles, int32_t n) {
+  if (!batch) return fail(FSLBM_EINVAL, "batch is NULL");
+  Batch &b = *(Batch *)batch;
+  if (!handles || n < 1) return fail(FSLBM_EINVAL, "no handles");
+  if (n > b.cap)
+    return fail(FSLBM_EINVAL, "batch reset: " + std::to_string(n) + " domains, the table space holds " +
+                                  std::to_string(b.cap));
+  std::vector<Ctx *> given(n);
+  for (int k = 0; k < n; ++k) {
+    if (!handles[k]) return fail(FSLBM_EINVAL, "a handle is NULL");
+    given[k] = (Ctx *)handles[k];
+    for (int j = 0; j < k; ++j)
+      if (given[j] == given[k]) return fail(FSLBM_EINVAL, "a handle is listed twice");
+    if (given[k]->P.precision != b.precision)
+      return fail(FSLBM_EINVAL, "all domains of a batch must have the same precision");
+    if (b.in_scratch && given[k]->stream != b.stream)
+      return fail(FSLBM_EINVAL, "every domain must have been created on the batch's stream");
+  }
+  // from now on steps are plain launches: the tables change in place
+  batch_drop_graphs(b);
+  b.direct = true;
+  b.dom = given;
+  long long cells = 0;
+  for (Ctx *c : given) cells += c->N;
+  b.info.cells = cells;
+  return batch_tables(b, b.info.bulk_threads);
 }
 
 int fslbm_batch_info_get(void *batch, fslbm_batch_info *out) {

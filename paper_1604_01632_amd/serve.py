@@ -8,8 +8,9 @@ admitted domains together as one batch (one graph launch per step) in
 quanta of steps.  A domain that reaches its horizon is read out (bubble
 table and scalars) and released, and its memory goes to the next request;
 requests arriving while others run join at the next quantum boundary, so
-their work overlaps on the device.  Scenes are built on host threads while
-the device runs.
+their work overlaps on the device.  Scenes are built, and domains uploaded
+on a side stream, by host threads while the device runs; the batch is
+kept for the whole run and its members are replaced in place.
 
 The plain baseline (``run_fifo``) serves the same arrival trace one domain
 at a time, first come first served, with the same kernels.
@@ -84,9 +85,17 @@ class Server:
     budget_bytes: device memory the admitted workspaces and the batch
     tables may use (default: 80 % of the free device memory at start); a
     request that could never fit is rejected (a Result with `error` set)
-    and the others keep running; max_active: slots; quantum:
-    steps between scheduling decisions (a domain never runs past its
-    horizon: a quantum ends at the next horizon).
+    and the others keep running; max_active: slots; quantum: steps between
+    scheduling decisions (a domain never runs past its horizon: a quantum
+    ends at the next horizon).
+
+    One batch lives for the whole run: admissions and completions replace
+    its members in place (``fslbm_batch_reset``), with no new batch, graph
+    or stream.  A request's scene is built on a host thread as soon as it
+    arrives; once admitted (memory reserved), its domain is created and
+    uploaded on a side stream by another host thread while the batch keeps
+    stepping, and it joins the batch at the next quantum boundary after its
+    upload finished.
     """
 
     def __init__(self, precision="fp32", budget_bytes=None, max_active=64, quantum=100,
@@ -108,28 +117,47 @@ class Server:
         return fslbm_workspace_bytes(p)
 
     def run(self, requests, clock=time.perf_counter, log=None) -> list:
+        import threading
+
+        import torch
+
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
-        waiting = collections.deque()  # arrived: (request, future scene)
+        waiting = collections.deque()   # arrived: (request, future scene)
+        creating = []                   # admitted: slots whose domain is being uploaded
         active, results = [], []
-        used = 0
+        tables = fslbm_batch_workspace_bytes(self.max_active)
+        used = tables
         batch = None
         pool = cf.ThreadPoolExecutor(max_workers=self.build_threads)
+        uploader = cf.ThreadPoolExecutor(max_workers=1)
+        side = {}
+        lock = threading.Lock()
+
+        def create(sc):
+            # one side stream per upload thread, default priority
+            tid = threading.get_ident()
+            with lock:
+                if tid not in side:
+                    side[tid] = torch.cuda.Stream()
+                st = side[tid]
+            with torch.cuda.stream(st):
+                return Domain.from_scene(sc, self.precision, stream=st, **self.overrides)
+
         t0 = clock()
         try:
-            while pending or waiting or active:
+            while pending or waiting or creating or active:
                 now = clock() - t0
                 while pending and pending[0].arrival <= now:
                     r = pending.popleft()
                     waiting.append((r, pool.submit(r.build)))
-                changed = False
-                while waiting and len(active) < self.max_active:
+                # admission by memory and slots, oldest first
+                while waiting and len(active) + len(creating) < self.max_active:
                     r, fut = waiting[0]
-                    if not fut.done() and active:
+                    if not fut.done() and (active or creating):
                         break  # keep the device busy while the scene is built
                     sc = fut.result()
                     need = self._need(sc)
-                    tables = fslbm_batch_workspace_bytes(len(active) + 1)
-                    if need == 0 or need + fslbm_batch_workspace_bytes(1) > self.budget:
+                    if need == 0 or need + tables > self.budget:
                         waiting.popleft()
                         t = clock() - t0
                         why = ("invalid parameters" if need == 0 else
@@ -139,48 +167,65 @@ class Server:
                         if log:
                             log(f"[serve] request {r.id} rejected: {why}")
                         continue
-                    if used + need + tables > self.budget:
+                    if used + need > self.budget:
                         break
                     waiting.popleft()
-                    dom = Domain.from_scene(sc, self.precision, **self.overrides)
-                    active.append(dict(req=r, dom=dom, left=r.horizon, need=need,
-                                       admitted=clock() - t0))
                     used += need
-                    changed = True
+                    creating.append(dict(req=r, fut=uploader.submit(create, sc), need=need,
+                                         admitted=clock() - t0, left=r.horizon))
+                # uploads that finished join the batch
+                joined = [s for s in creating if s["fut"].done()]
+                if not active and not joined and creating:
+                    creating[0]["fut"].result()  # nothing to step: wait for the next upload
+                    joined = [s for s in creating if s["fut"].done()]
+                for s in joined:
+                    s["dom"] = s.pop("fut").result()
+                    creating.remove(s)
+                    active.append(s)
                 if not active:
                     if waiting:
                         waiting[0][1].result()
                     elif pending:
                         time.sleep(max(0.0, pending[0].arrival - (clock() - t0)))
                     continue
-                if changed or batch is None:
-                    if batch is not None:
-                        batch.close()
-                    batch = Batch([s["dom"] for s in active], tuning_cache_path="")
+                doms = [s["dom"] for s in active]
+                if batch is None:
+                    batch = Batch(doms, tuning_cache_path="", capacity=self.max_active)
+                elif joined or batch.domains != doms:
+                    batch.reset(doms)
                 q = min(self.quantum, min(s["left"] for s in active))
                 batch.step(q)
                 for s in active:
                     s["left"] -= q
                 done = [s for s in active if s["left"] == 0]
+                for s in done:
+                    s["dom"].sync()  # its last quantum has finished on the device
+                    res = _finish(s, clock() - t0)
+                    results.append(res)
+                    if log:
+                        log(f"[serve] request {res.id} done: latency {res.latency:.2f} s, "
+                            f"{res.cells} cells x {res.steps} steps")
+                active = [s for s in active if s["left"] > 0]
                 if done:
+                    # the batch no longer holds the finished domains before
+                    # their memory goes back
+                    if active:
+                        batch.reset([s["dom"] for s in active])
                     for s in done:
-                        s["dom"].sync()  # its last quantum has finished on the device
-                        res = _finish(s, clock() - t0)
-                        results.append(res)
                         s["dom"].close()
                         used -= s["need"]
-                        if log:
-                            log(f"[serve] request {res.id} done: latency {res.latency:.2f} s, "
-                                f"{res.cells} cells x {res.steps} steps")
-                    active = [s for s in active if s["left"] > 0]
-                    batch.close()
-                    batch = None
-                else:
+                if not done:
                     active[0]["dom"].sync()  # bound the queue ahead of the clock
         finally:
             if batch is not None:
                 batch.close()
+            for s in creating:
+                try:
+                    s["fut"].result().close()
+                except Exception:
+                    pass
             pool.shutdown(wait=True)
+            uploader.shutdown(wait=True)
         return results
 
 

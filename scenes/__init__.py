@@ -358,6 +358,29 @@ def thread_lattice(n=(256, 256, 256), spacing=64, R=8.0, amp=0.1, wavelength=72.
                  dict(spacing=spacing, R=R, amp=amp, wavelength=wavelength))
 
 
+def gas_prism(n=(360, 40, 40), size=(336, 8, 8), tau=0.51, sigma=1e-2, steps=630000,
+              name="prism"):
+    """A rectangular gas region of `size` cells centred in a periodic box of
+    liquid (the thread of the paper's rupture example, Sec. 3.1: 336 x 8 x 8
+    cells in 360 x 40 x 40).  The region is aligned with the cell faces, so
+    its cells are gas and the liquid cells around it become full interface
+    cells (closed layer).  The liquid starts at the Laplace density of a
+    cylinder of the same cross-section area, rho = 1 - 3 sigma / R_eq with
+    R_eq = sqrt(a b / pi), the gas at p0."""
+    nx, ny, nz = n
+    x, y, z = _grid(nx, ny, nz)
+    lo = [(m - s) // 2 for m, s in zip(n, size)]
+    inside = ((x >= lo[0]) & (x < lo[0] + size[0]) & (y >= lo[1]) & (y < lo[1] + size[1])
+              & (z >= lo[2]) & (z < lo[2] + size[2]))
+    phi = np.where(inside, 0.0, 1.0)
+    r_eq = math.sqrt(size[1] * size[2] / math.pi)
+    rho = np.full(nx * ny * nz, 1.0 - 3.0 * sigma / r_eq)
+    return _finish(name, nx, ny, nz, (1, 1, 1), phi, np.full(nx * ny * nz, 255, np.uint8), rho,
+                   tau, sigma, (0.0, 0.0, 0.0), 1e-2, 0.0,
+                   lambda px, py, pz: np.zeros(px.shape, dtype=np.int64), lambda b: P0, steps,
+                   meta=dict(size=size, r_eq=r_eq))
+
+
 def orifice(n=(128, 128, 256), r=6.0, g=1e-5, tau=0.6, sigma=2e-3, Q=0.05, steps=50000,
             name="orifice"):
     """Closed box with wall layers on all faces; the bottom wall is pierced by

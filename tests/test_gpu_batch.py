@@ -131,3 +131,38 @@ def test_larger_domain_alone_equals_batch_of_one(case):
         say(f"[alone-vs-batch] {case}: {done} steps, bubbles {len(alone.bubbles()['id'])}")
         _same(alone, other, f"{case} after {done} steps")
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_reset_members_come_and_go(precision):
+    """A batch whose members change (fslbm_batch_reset: a serving loop's
+    admissions and completions) keeps computing what each domain computes
+    alone, bit for bit: members leave, join, rejoin with another parity."""
+    from paper_1604_01632_amd import Batch, Domain
+
+    scs = _scenes()[:4]
+    alone = [Domain.from_scene(sc, precision) for sc in scs]
+    mixed = [Domain.from_scene(sc, precision) for sc in scs]
+    steps = [0] * len(scs)
+    b = Batch(mixed[:2], tuning_cache_path="", capacity=len(scs))
+
+    def run(members, n):
+        b.step(n)
+        for k in members:
+            steps[k] += n
+
+    run([0, 1], 7)
+    b.reset([mixed[1], mixed[2]])
+    run([1, 2], 4)
+    mixed[3].step(3)  # stepped alone before it joins: another parity
+    steps[3] += 3
+    b.reset([mixed[3], mixed[0], mixed[1], mixed[2]])
+    run([3, 0, 1, 2], 5)
+    b.reset([mixed[2]])
+    run([2], 2)
+    with pytest.raises(Exception):
+        b.reset(mixed + [Domain.from_scene(scs[0], precision)])  # beyond the capacity
+    b.close()
+    for k, (a, m) in enumerate(zip(alone, mixed)):
+        a.step(steps[k])
+        _same(a, m, f"reset member {k} after {steps[k]} steps")
