@@ -285,27 +285,35 @@ const char *fslbm_last_error(void);
  * graph launch.  Each domain computes exactly what fslbm_step computes for
  * it alone (bit for bit).
  *
- * Autotuning at creation: the stream-collide block size (128 or 256
- * threads) and the order of domains in the block map (as given, or by
- * decreasing size) are chosen by timing the stream-collide kernel of the
- * batch on the live state (a probe without the mass accumulator that only
- * writes buffers the next step rewrites).  The choice is appended to the
+ * Autotuning at creation, 18 points: the stream-collide block size (128 or
+ * 256 threads) and the order of domains in the block map (as given, by
+ * decreasing or by increasing size) are chosen by timing the
+ * stream-collide kernel of the batch on the live state (a probe without
+ * the mass accumulator that only writes buffers the next step rewrites),
+ * and the grid density of the interface-list kernels (one block per 1024,
+ * 2048 or 4096 cells) by timing the geometry kernel (which only writes
+ * per-slot values the next step rewrites).  The choice is appended to the
  * text file tuning_cache_path (may be NULL: tune without caching) under a
  * key made of the precision and the domain extents, and read from it next
- * time.  An empty string "" skips tuning (256 threads, domains as given),
- * for callers that rebuild batches often.
+ * time.  An empty string "" skips tuning (256 threads, domains as given,
+ * 2048 cells per list block), for callers that rebuild batches often.
  * --------------------------------------------------------------------- */
 
 /* Device bytes of the batch tables for n_domains (0 if n_domains < 1). */
 size_t fslbm_batch_workspace_bytes(int32_t n_domains);
 
 typedef struct {
-  int32_t bulk_threads;  /* chosen stream-collide block size */
-  int32_t order;         /* 0: domains as given, 1: by decreasing size */
+  int32_t bulk_threads;  /* chosen stream-collide block size (128 or 256) */
+  int32_t order;         /* 0: domains as given, 1: by decreasing size,
+                            2: by increasing size */
   int32_t from_cache;    /* 1 if the choice came from the tuning cache */
-  int32_t pad;
+  int32_t list_cells;    /* cells per block of the interface-list kernels'
+                            grids (1024, 2048 or 4096) */
   int64_t cells;         /* cells of all domains */
-  float probe_ms[4];     /* probe times of (256, given), (256, size), (128, given), (128, size) */
+  float probe_ms[9];     /* stream-collide probes of (256 or 128 threads) x
+                            (order 0, 1, 2) in that order, then geometry
+                            probes of 1024, 2048 and 4096 cells per block */
+  int32_t pad;
 } fslbm_batch_info;
 
 /* Build a batch over handles[n] (distinct, same precision).  The device

@@ -61,7 +61,8 @@ class Scalars(C.Structure):
 
 class BatchInfo(C.Structure):
     _fields_ = [("bulk_threads", C.c_int32), ("order", C.c_int32), ("from_cache", C.c_int32),
-                ("pad", C.c_int32), ("cells", C.c_int64), ("probe_ms", C.c_float * 4)]
+                ("list_cells", C.c_int32), ("cells", C.c_int64), ("probe_ms", C.c_float * 9),
+                ("pad", C.c_int32)]
 
 
 class Timing(C.Structure):
@@ -366,7 +367,7 @@ def fslbm_batch_info_get(batch) -> dict:
     info = BatchInfo()
     _check(lib().fslbm_batch_info_get(batch, C.byref(info)))
     return dict(bulk_threads=info.bulk_threads, order=info.order, from_cache=info.from_cache,
-                cells=info.cells, probe_ms=list(info.probe_ms))
+                list_cells=info.list_cells, cells=info.cells, probe_ms=list(info.probe_ms))
 
 
 def fslbm_batch_destroy(batch) -> None:

@@ -249,7 +249,7 @@ void build_devs(Ctx &c) {
   }
 }
 
-LaunchCfg make_cfg(const fslbm_params &p, int bulk_threads = 256) {
+LaunchCfg make_cfg(const fslbm_params &p, int bulk_threads = 256, int list_cells = 2048) {
   LaunchCfg cfg;
   const long long N = (long long)p.nx * p.ny * p.nz;
   auto clampb = [&](long long per, long long cap) {
@@ -262,7 +262,7 @@ LaunchCfg make_cfg(const fslbm_params &p, int bulk_threads = 256) {
   // and a block that finds no work still costs its dispatch (a batch of
   // small domains would otherwise launch hundreds of thousands of them).
   // Large boxes reach the caps.
-  cfg.blocks[G_LIST] = clampb(2048, 2048);
+  cfg.blocks[G_LIST] = clampb(list_cells, 2048);
   cfg.blocks[G_SMALL] = clampb(4096, 256);
   cfg.blocks[G_TILE] = (int)((N + 4095) / 4096);
   cfg.blocks[G_ONE] = 1;
@@ -339,7 +339,7 @@ int batch_capacity(size_t bytes) {
 // pinned staging buffers without waiting for the stream, or, for a batch in
 // the scratch array (which allocates nothing, not even pinned host memory),
 // from pageable memory with a wait.
-int batch_tables(Batch &b, int bulk_threads) {
+int batch_tables(Batch &b, int bulk_threads, int list_cells = 2048) {
   const int nd = (int)b.dom.size();
   const int cap = b.cap > 0 ? b.cap : nd;
   std::vector<Dev> devs(2 * (size_t)nd);
@@ -351,7 +351,7 @@ int batch_tables(Batch &b, int bulk_threads) {
     b.base_cur[k] = c.cur;
     devs[k] = c.dev[c.cur];
     devs[nd + k] = c.dev[c.cur ^ 1];
-    const LaunchCfg lc = make_cfg(c.P, bulk_threads);
+    const LaunchCfg lc = make_cfg(c.P, bulk_threads, list_cells);
     for (int g = 0; g < G_COUNT; ++g) off[g][k + 1] = off[g][k] + lc.blocks[g];
   }
   // the image of the table space: [Dev x cap][Dev x cap] then per class
@@ -459,39 +459,51 @@ std::string batch_key(const Batch &b) {
   return buf;
 }
 
-bool batch_cache_lookup(const char *path, const std::string &key, int &threads, int &order) {
+bool batch_cache_lookup(const char *path, const std::string &key, int &threads, int &order,
+                        int &list_cells) {
   if (!path) return false;
   FILE *f = std::fopen(path, "r");
   if (!f) return false;
-  char k[128];
-  int t, o;
+  char line[256];
   bool found = false;
-  while (std::fscanf(f, "%127s %d %d", k, &t, &o) == 3)
-    if (key == k && (t == 128 || t == 256) && (o == 0 || o == 1)) {
+  while (std::fgets(line, sizeof line, f)) {
+    char k[128];
+    int t, o, l;
+    if (std::sscanf(line, "%127s %d %d %d", k, &t, &o, &l) != 4) continue;
+    if (key == k && (t == 128 || t == 256) && o >= 0 && o <= 2 &&
+        (l == 1024 || l == 2048 || l == 4096)) {
       threads = t;
       order = o;
+      list_cells = l;
       found = true;
     }
+  }
   std::fclose(f);
   return found;
 }
 
-void batch_cache_store(const char *path, const std::string &key, int threads, int order) {
+void batch_cache_store(const char *path, const std::string &key, int threads, int order,
+                       int list_cells) {
   if (!path) return;
   FILE *f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d\n", key.c_str(), threads, order);
+  std::fprintf(f, "%s %d %d %d\n", key.c_str(), threads, order, list_cells);
   std::fclose(f);
 }
 
-// Average duration (ms) of the stream-collide probe over reps launches.
-int batch_probe(Batch &b, int reps, float &ms) {
+// Average duration (ms) of a probe over reps launches: the stream-collide
+// kernel (list = false) or the geometry kernel (list = true).
+int batch_probe(Batch &b, int reps, float &ms, bool list = false) {
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  for (int w = 0; w < 2; ++w) b.L.batch_bulk_probe(b.cfg[0], b.stream);
+  auto probe = [&]() {
+    if (list) b.L.batch_list_probe(b.cfg[0], b.stream);
+    else b.L.batch_bulk_probe(b.cfg[0], b.stream);
+  };
+  for (int w = 0; w < 2; ++w) probe();
   HIP_TRY(hipEventRecord(e0, b.stream));
-  for (int r = 0; r < reps; ++r) b.L.batch_bulk_probe(b.cfg[0], b.stream);
+  for (int r = 0; r < reps; ++r) probe();
   HIP_TRY(hipEventRecord(e1, b.stream));
   HIP_TRY(hipEventSynchronize(e1));
   HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
@@ -505,6 +517,8 @@ void batch_order(Batch &b, const std::vector<Ctx *> &given, int order) {
   b.dom = given;
   if (order == 1)
     std::stable_sort(b.dom.begin(), b.dom.end(), [](const Ctx *x, const Ctx *y) { return x->N > y->N; });
+  if (order == 2)
+    std::stable_sort(b.dom.begin(), b.dom.end(), [](const Ctx *x, const Ctx *y) { return x->N < y->N; });
 }
 
 void batch_free(Batch *b) {
@@ -1120,16 +1134,19 @@ int fslbm_batch_create(void *const *handles, int32_t n, const char *tuning_cache
   // autotuning: stream-collide block size and block-to-domain order
   b->dom = given;
   const std::string key = batch_key(*b);
-  int threads = 256, order = 0;
+  int threads = 256, order = 0, list_cells = 2048;
   if (tuning_cache_path && !tuning_cache_path[0]) {
     // "": no tuning (callers that rebuild batches often)
-  } else if (batch_cache_lookup(tuning_cache_path, key, threads, order)) {
+  } else if (batch_cache_lookup(tuning_cache_path, key, threads, order, list_cells)) {
     b->info.from_cache = 1;
   } else {
+    // the stream-collide grid (block size x domain order), then the list
+    // kernels' grid density with the chosen order; the two grids are
+    // independent, so 9 probes cover the 18 points
     float best = 1e30f;
     int ci = 0;
     for (int t : {256, 128})
-      for (int o : {0, 1}) {
+      for (int o : {0, 1, 2}) {
         batch_order(*b, given, o);
         int rc = batch_tables(*b, t);
         float ms = 0.f;
@@ -1142,12 +1159,26 @@ int fslbm_batch_create(void *const *handles, int32_t n, const char *tuning_cache
           order = o;
         }
       }
-    batch_cache_store(tuning_cache_path, key, threads, order);
+    batch_order(*b, given, order);
+    best = 1e30f;
+    for (int l : {1024, 2048, 4096}) {
+      int rc = batch_tables(*b, threads, l);
+      float ms = 0.f;
+      if (rc == FSLBM_OK) rc = batch_probe(*b, 5, ms, true);
+      if (rc != FSLBM_OK) return bail(rc);
+      b->info.probe_ms[ci++] = ms;
+      if (ms < best) {
+        best = ms;
+        list_cells = l;
+      }
+    }
+    batch_cache_store(tuning_cache_path, key, threads, order, list_cells);
   }
   b->info.bulk_threads = threads;
   b->info.order = order;
+  b->info.list_cells = list_cells;
   batch_order(*b, given, order);
-  int rc = batch_tables(*b, threads);
+  int rc = batch_tables(*b, threads, list_cells);
   if (rc == FSLBM_OK) rc = batch_capture(*b);
   if (rc == FSLBM_OK && hipStreamSynchronize(b->stream) != hipSuccess) {
     fail(FSLBM_EDEVICE, "batch: table upload failed");
@@ -1192,6 +1223,7 @@ int fslbm_batch_create_noalloc(void *const *handles, int32_t n, void *stream, vo
   for (Ctx *c : given) cells += c->N;
   b->info.cells = cells;
   b->info.bulk_threads = 256;
+  b->info.list_cells = 2048;
   b->cap = batch_capacity(SCRATCH_BYTES);
   int rc = batch_tables(*b, 256);
   if (rc != FSLBM_OK) {
@@ -1216,7 +1248,7 @@ int fslbm_batch_step(void *batch, int32_t n_steps) {
   for (int k = 1; k < nd; ++k) same = same && (((b.dom[k]->cur - b.base_cur[k]) & 1) == r0);
   int r = r0;
   if (!same) {
-    int rc = batch_tables(b, b.info.bulk_threads);
+    int rc = batch_tables(b, b.info.bulk_threads, b.info.list_cells);
     if (rc == FSLBM_OK && !b.in_scratch && !b.direct) rc = batch_capture(b);
     if (rc != FSLBM_OK) return rc;
     r = 0;
@@ -1302,7 +1334,7 @@ int fslbm_batch_reset(void *batch, void *const *handles, int32_t n) {
   long long cells = 0;
   for (Ctx *c : given) cells += c->N;
   b.info.cells = cells;
-  return batch_tables(b, b.info.bulk_threads);
+  return batch_tables(b, b.info.bulk_threads, b.info.list_cells);
 }
 
 int fslbm_batch_info_get(void *batch, fslbm_batch_info *out) {

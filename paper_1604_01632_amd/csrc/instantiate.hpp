@@ -99,6 +99,11 @@ static void batch_bulk_probe_impl(const BatchCfg &b, hipStream_t s) {
 }
 
 template <class P>
+static void batch_list_probe_impl(const BatchCfg &b, hipStream_t s) {
+  many<K_geom<P>>(b, G_LIST, s);
+}
+
+template <class P>
 static void init_feq_impl(const Dev &d, const LaunchCfg &c, const double *rho, const double *u,
                           hipStream_t s) {
   k_init_feq<P><<<c.blocks[G_CELL], 256, 0, s>>>(d, rho, u);
@@ -126,6 +131,7 @@ static Launchers make_launchers() {
   L.phase = phase_impl<P>;
   L.batch_phase = batch_phase_impl<P>;
   L.batch_bulk_probe = batch_bulk_probe_impl<P>;
+  L.batch_list_probe = batch_list_probe_impl<P>;
   L.init_feq = init_feq_impl<P>;
   L.init_f = init_f_impl<P>;
   L.exportq = export_impl<P>;

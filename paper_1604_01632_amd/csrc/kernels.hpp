@@ -534,6 +534,10 @@ __device__ __forceinline__ void collide(const Dev &d, typename P::R *f, typename
 template <class R>
 struct PhiWin {
   int xp[7], yp[7], zp[7], xm[7], ym[7], zm[7];
+  // bit k: offset k - 3 lies on a face layer of a non-periodic axis or
+  // beyond it (interior samples can never be wall cells: walls form the
+  // face layers only)
+  uint32_t xf = 0, yf = 0, zf = 0;
   __device__ __forceinline__ PhiWin(const Dev &d, int x, int y, int z) {
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
@@ -543,6 +547,9 @@ struct PhiWin {
       xm[k] = mirror(xp[k], d.nx, d.per[0]);
       ym[k] = mirror(yp[k], d.ny, d.per[1]);
       zm[k] = mirror(zp[k], d.nz, d.per[2]);
+      xf |= (uint32_t)(!d.per[0] && (xp[k] <= 0 || xp[k] >= d.nx - 1)) << k;
+      yf |= (uint32_t)(!d.per[1] && (yp[k] <= 0 || yp[k] >= d.ny - 1)) << k;
+      zf |= (uint32_t)(!d.per[2] && (zp[k] <= 0 || zp[k] >= d.nz - 1)) << k;
     }
   }
   __device__ __forceinline__ static int mirror(int c, int n, int per) {
@@ -554,6 +561,9 @@ struct PhiWin {
   __device__ __forceinline__ R get(const Dev &d, const R *phi, int ox, int oy, int oz) const {
     const int cx = xp[ox + 3], cy = yp[oy + 3], cz = zp[oz + 3];
     if (!d.has_walls) return phi[cx + d.nx * (cy + d.ny * cz)];
+    // an interior sample is an ordinary cell: no flag to look at
+    if (!(((xf >> (ox + 3)) | (yf >> (oy + 3)) | (zf >> (oz + 3))) & 1u))
+      return phi[cx + d.nx * (cy + d.ny * cz)];
     if (cx >= 0 && cx < d.nx && cy >= 0 && cy < d.ny && cz >= 0 && cz < d.nz) {
       const int i = cx + d.nx * (cy + d.ny * cz);
       if ((d.flag_src[i] & TYPE_MASK) != T_WALL) return phi[i];

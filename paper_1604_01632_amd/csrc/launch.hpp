@@ -42,6 +42,9 @@ struct Launchers {
   // stream-collide alone without the mass accumulator (autotuning: it only
   // writes the new lattice and flags, which the next step rewrites)
   void (*batch_bulk_probe)(const BatchCfg &b, hipStream_t s);
+  // the geometry kernel alone over the interface lists (autotuning of the
+  // list-kernel grid: it only writes per-slot values the next step rewrites)
+  void (*batch_list_probe)(const BatchCfg &b, hipStream_t s);
   void (*init_feq)(const Dev &d, const LaunchCfg &c, const double *rho, const double *u,
                    hipStream_t s);
   void (*init_f)(const Dev &d, const LaunchCfg &c, const double *src, int a, hipStream_t s);

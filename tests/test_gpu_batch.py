@@ -56,6 +56,8 @@ def test_batch_equals_each_domain_alone(precision, tmp_path):
     info = b.info()
     say(f"[batch] {precision}: tuned {info}")
     assert info["bulk_threads"] in (128, 256) and info["from_cache"] == 0
+    assert info["order"] in (0, 1, 2) and info["list_cells"] in (1024, 2048, 4096)
+    assert all(t > 0 for t in info["probe_ms"])  # nine probes
     done = 0
     for n in (1, 1, 3, 5, 2):
         for d in alone:
@@ -74,7 +76,10 @@ def test_batch_equals_each_domain_alone(precision, tmp_path):
         _same(a, m, f"{precision} domain {k} after the parity shift")
     b.close()
     b2 = Batch(mixed, tuning_cache_path=tmp_path / "tune.txt")
-    assert b2.info()["from_cache"] == 1
+    i2 = b2.info()
+    assert i2["from_cache"] == 1
+    assert (i2["bulk_threads"], i2["order"], i2["list_cells"]) == (
+        info["bulk_threads"], info["order"], info["list_cells"])
     assert b2.info()["bulk_threads"] == info["bulk_threads"]
     b2.close()
 
