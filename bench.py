@@ -413,13 +413,22 @@ def bench_served(args) -> int:
     reqs = [serve.Request(d["id"], float(a), d["horizon"], (lambda k=k: built[k]))
             for k, (d, a) in enumerate(zip(descs, arrivals))]
     log(f"[bench] served: {len(reqs)} requests, capacity {cap_mlups:.0f} MLUPS, rate {rate:.3f}/s")
+    def progress(tag):
+        n = [0]
+
+        def f(msg):
+            n[0] += 1
+            if n[0] % 32 == 0:
+                log(f"[bench] {tag}: {n[0]} requests done")
+        return f
+
     srv = serve.Server("fp32", max_active=args.max_active, quantum=args.quantum)
     t0 = time.perf_counter()
-    res = srv.run(reqs)
+    res = srv.run(reqs, log=progress("continuous batching"))
     s_srv = serve.summary(res, time.perf_counter() - t0)
     log(f"[bench] continuous batching: {s_srv}")
     t0 = time.perf_counter()
-    res_fifo = serve.run_fifo(reqs, "fp32")
+    res_fifo = serve.run_fifo(reqs, "fp32", log=progress("plain loop"))
     s_fifo = serve.summary(res_fifo, time.perf_counter() - t0)
     log(f"[bench] plain loop: {s_fifo}")
     by = {r.id: r for r in res_fifo}
