@@ -2099,12 +2099,34 @@ struct K_label_assign {
     d.b_ratio[s] = v > 0.0 ? d.b_vstar[s] / v : -(d.b_vstar[s] / (double)(nc > 0 ? nc : 1));
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int k = 0;
-    for (int s = 0; s < B && k < nnew; ++s) {
-      const bool stays = d.b_live[s] && d.b_kept[s];
-      if (!stays) d.newslot[k++] = s;
+  // the first nnew free slots in increasing order: a block-wide prefix
+  // count of the free slots, chunk by chunk
+  __shared__ int wfree[THREADS / 64];
+  __shared__ int s_base;
+  if (threadIdx.x == 0) s_base = 0;
+  __syncthreads();
+  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+  for (int s0 = 0; s0 < B; s0 += THREADS) {
+    const int s = s0 + (int)threadIdx.x;
+    const bool freed = s < B && !(d.b_live[s] && d.b_kept[s]);
+    const unsigned long long m = __ballot(freed);
+    if (lane == 0) wfree[w] = __popcll(m);
+    __syncthreads();
+    int before = s_base;
+    for (int k = 0; k < w; ++k) before += wfree[k];
+    const int pos = before + (int)__popcll(m & ((1ull << lane) - 1ull));
+    if (freed && pos < nnew) d.newslot[pos] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int k = 0; k < THREADS / 64; ++k) t += wfree[k];
+      s_base += t;
     }
+    __syncthreads();
+    if (s_base >= nnew) break;  // uniform: read by every thread after the barrier
+  }
+  if (threadIdx.x == 0) {
+    const int k = s_base < nnew ? s_base : nnew;
     if (k < nnew) sc->err |= ERR_CAPACITY;
     sc->nfree = k;
   }
@@ -2172,9 +2194,27 @@ struct K_label_accumulate {
 
 // ------------------------------------------------------------- k_bubbles
 
+// One new component k of a labelling run, with its summed accumulator
+// words a[NACC], into its slot.
+__device__ __forceinline__ void install_one(const Dev &d, int k, const unsigned long long *a) {
+  const int s = d.newslot[k];
+  d.b_id[s] = d.sc->next_id + k;
+  long long wv[EX_WORDS], ws[EX_WORDS];
+  for (int c = 0; c < EX_WORDS; ++c) {
+    wv[c] = ll(a[c]);
+    ws[c] = ll(a[EX_WORDS + c]);
+  }
+  d.b_flags[s] = ll(a[2 * EX_WORDS + 3]) > 0 ? 1 : 0;
+  d.b_vol[s] = ex_value(wv);
+  d.b_vstar[s] = ex_value(ws);
+  d.b_ngas[s] = ll(a[2 * EX_WORDS + 1]);
+  d.b_niface[s] = ll(a[2 * EX_WORDS + 2]);
+  d.b_live[s] = 1;
+}
+
 // After a labelling run (one block): free the slots of replaced bubbles
 // and install the new components (summing and clearing their partial
-// sums).
+// sums).  Every thread of the block must call it.
 __device__ __forceinline__ void install_new_bubbles(const Dev &d) {
   Scalars *sc = d.sc;
   const int nnew = sc->nnew;
@@ -2182,29 +2222,30 @@ __device__ __forceinline__ void install_new_bubbles(const Dev &d) {
   for (int s = threadIdx.x; s < B; s += blockDim.x)
     if (d.b_live[s] && !d.b_kept[s]) d.b_live[s] = 0;
   __syncthreads();
-  for (int k = threadIdx.x; k < nnew; k += blockDim.x) {
-    unsigned long long a[NACC];
-    for (int c = 0; c < NACC; ++c) a[c] = 0;
-    unsigned long long *p = d.c_acc + (long long)k * SUB * NACC;
-    for (int u = 0; u < SUB * NACC; ++u) {
-      a[u % NACC] += p[u];
-      p[u] = 0;
+  // the SUB partial sums of every word of every new component, one thread
+  // per (component, word), through shared memory (a component at a time per
+  // thread would walk its SUB * NACC words in series)
+  __shared__ unsigned long long comp_sum[64][NACC];
+  for (int k0 = 0; k0 < nnew; k0 += 64) {
+    const int kn = nnew - k0 < 64 ? nnew - k0 : 64;
+    for (int t = threadIdx.x; t < kn * NACC; t += blockDim.x) {
+      const int k = k0 + t / NACC, c = t % NACC;
+      unsigned long long *p = d.c_acc + (long long)k * SUB * NACC + c;
+      unsigned long long v[SUB];
+#pragma unroll
+      for (int u = 0; u < SUB; ++u) v[u] = p[u * NACC];
+      unsigned long long acc = 0;
+#pragma unroll
+      for (int u = 0; u < SUB; ++u) {
+        acc += v[u];
+        p[u * NACC] = 0;
+      }
+      comp_sum[t / NACC][c] = acc;
     }
-    const int s = d.newslot[k];
-    d.b_id[s] = sc->next_id + k;
-    long long wv[EX_WORDS], ws[EX_WORDS];
-    for (int c = 0; c < EX_WORDS; ++c) {
-      wv[c] = ll(a[c]);
-      ws[c] = ll(a[EX_WORDS + c]);
-    }
-    d.b_flags[s] = ll(a[2 * EX_WORDS + 3]) > 0 ? 1 : 0;
-    d.b_vol[s] = ex_value(wv);
-    d.b_vstar[s] = ex_value(ws);
-    d.b_ngas[s] = ll(a[2 * EX_WORDS + 1]);
-    d.b_niface[s] = ll(a[2 * EX_WORDS + 2]);
-    d.b_live[s] = 1;
+    __syncthreads();
+    for (int kk = threadIdx.x; kk < kn; kk += blockDim.x) install_one(d, k0 + kk, comp_sum[kk]);
+    __syncthreads();
   }
-  __syncthreads();
   if (threadIdx.x == 0) {
     sc->next_id += nnew;
     if (nnew > 0) sc->n_topology += 1;
