@@ -372,6 +372,102 @@ def bench_forms(args) -> int:
     return 0
 
 
+# Detachment volumes of Sec. 3.2 (Table tab:detRad), mm^3: the paper's own
+# FSLBM runs and the two comparison results it quotes, at 1 ml/min (the
+# analytic one for a vanishing flow rate).  Context for the trend only: the
+# runs here use a similarity mapping, not the paper's time step.
+PORE_TABLE = {70.0: {"paper_fslbm": 38.0, "vof_2d": 39.0, "analytic_q0": 33.0},
+              90.0: {"paper_fslbm": 51.0, "vof_2d": 69.0, "analytic_q0": 69.0}}
+
+
+def first_detachment(sc, precision, max_steps, check_every, log_every=20):
+    """Step a pore scene until the first bubble without inlet or atmosphere
+    flag appears (a bubble pinched off the pore); returns (steps, its volume
+    in cells, seconds of device time, detached before max_steps)."""
+    import torch
+
+    import paper_1604_01632_amd as F
+
+    dom = F.Domain.from_scene(sc, precision)
+    done, vol, found = 0, 0.0, False
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k = 0
+    while done < max_steps and not found:
+        dom.step(check_every)
+        done += check_every
+        b = dom.bubbles()
+        free = [v for f, v in zip(b["flags"], b["volume"]) if int(f) == 0]
+        if free:
+            found, vol = True, float(max(free))
+        k += 1
+        if k % log_every == 0:
+            inlet = [round(float(v), 1) for f, v in zip(b["flags"], b["volume"]) if int(f) & 1]
+            log(f"[bench] pore theta={sc.contact_angle:g} q={sc.meta['q_ml_min']:g}: {done} steps, "
+                f"inlet bubble {inlet} cells")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dom.close()
+    del dom
+    torch.cuda.empty_cache()
+    return done, vol, dt, found
+
+
+def bench_pore(args) -> int:
+    """The pore case of Sec. 3.2: gas blown through a pore of radius r in
+    the bottom wall into liquid under gravity, with an open top (atmosphere
+    bubble at p0) and a static contact angle at the walls.  For contact
+    angles 70 and 90 degrees and flow rates 1 and 10 ml/min, the first
+    detached bubble's volume in mm^3, by the similarity mapping (Bond number
+    of water-air at the 1 mm orifice, flow rate per capillary time), next to
+    the paper's table."""
+    import torch
+
+    import scenes
+
+    torch.cuda.set_device(0)
+    r = args.pore_radius
+    units = scenes.pore_units_similar(r)
+    runs, cells_steps, secs = [], 0.0, 0.0
+    for theta in (70.0, 90.0):
+        for q in (1.0, 10.0):
+            sc = scenes.pore(r=r, theta=theta, q_ml_min=q, tau=0.6, units=units)
+            # volume flow per step in cells: detachment below 200 r^3
+            max_steps = int(200 * r ** 3 / sc.inject_rate)
+            steps, vol, dt, found = first_detachment(sc, args.precision, max_steps, 1000)
+            cells_steps += sc.n * steps
+            secs += dt
+            row = {"theta": theta, "q_ml_min": q, "detached": found, "steps": steps,
+                   "v_d_cells": round(vol, 1), "v_d_mm3": round(vol * units["mm3_per_cell"], 2),
+                   "t_d_ms": round(steps * units["dt"] * 1e3, 1),
+                   "mlups": round(sc.n * steps / dt / 1e6, 1)}
+            runs.append(row)
+            log(f"[bench] pore: {row}")
+    v = {(row["theta"], row["q_ml_min"]): row["v_d_mm3"] for row in runs}
+    out = {
+        "metric": METRIC, "value": round(cells_steps / secs / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": int(sum(row["steps"] for row in runs)), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16dev": "f16dev"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"pore detachment (Sec. 3.2): {sc.nx}x{sc.ny}x{sc.nz} walled box, "
+                               f"pore r = {r} cells (1 mm), open top (atmosphere at p0), "
+                               "contact angle 70/90 deg, 1 and 10 ml/min, Bond number "
+                               f"{units['bond']:.4f} and flow per capillary time of water-air, "
+                               f"sigma {units['sigma']}, tau 0.6, {args.precision}; each run to "
+                               "its first detachment",
+                   "runs": runs,
+                   "trend_70_below_90": all(v[(70.0, q)] < v[(90.0, q)] for q in (1.0, 10.0)),
+                   "trend_rate_increases_volume": all(v[(t, 1.0)] < v[(t, 10.0)] for t in (70.0, 90.0)),
+                   "paper_table_mm3": {str(int(t)): row for t, row in PORE_TABLE.items()},
+                   "units": {k: units[k] for k in ("dx", "dt", "g", "sigma", "bond",
+                                                   "capillary_time_steps", "mm3_per_cell")}},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_served(args) -> int:
     """Served form: a Poisson stream of foam requests at 80 % of the measured
     capacity, continuous batching against the plain first-come-first-served
@@ -464,7 +560,8 @@ def main() -> int:
                     help="steps run before the warm-up (default: the rupture epoch of p1, "
                          f"step {RUPTURE_START}; 0 for other workloads)")
     ap.add_argument("--workload", default="p1",
-                    help="p1 (default: 256^3 thread rupture), c1/c2/c3, batched, served, forms")
+                    help="p1 (default: 256^3 thread rupture), c1/c2/c3, batched, served, forms, "
+                         "pore")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16dev"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -482,6 +579,7 @@ def main() -> int:
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter scaling) and exit")
     ap.add_argument("--domains", type=int, default=256, help="batched workload: domains")
+    ap.add_argument("--pore-radius", type=int, default=10, help="pore workload: pore radius in cells")
     ap.add_argument("--plain-steps", type=int, default=50,
                     help="batched workload: steps of the plain per-domain loop")
     ap.add_argument("--requests", type=int, default=512, help="served workload: requests")
@@ -508,6 +606,8 @@ def main() -> int:
         return bench_served(args)
     if args.workload == "forms":
         return bench_forms(args)
+    if args.workload == "pore":
+        return bench_pore(args)
 
     import numpy as np
     import torch

@@ -74,8 +74,12 @@ enum { FSLBM_FP64 = 0, FSLBM_FP32 = 1, FSLBM_FP16DEV = 2 };
 /* Collision operator: BGK (Sec. 2.1) or two-relaxation-time. */
 enum { FSLBM_BGK = 0, FSLBM_TRT = 1 };
 
-/* Bubble flag bits. */
-enum { FSLBM_BUBBLE_INLET = 1 };
+/* Bubble flag bits: INLET the bubble owns inlet cells (gas is injected,
+ * Sec. 3.2); ATMOSPHERE the bubble is held at the reference pressure p0
+ * whatever its volume (the open top of the pore case, Sec. 3.2).  A
+ * component formed by a merge or split owns inlet cells if it holds one,
+ * and is an atmosphere if it holds cells of an atmosphere. */
+enum { FSLBM_BUBBLE_INLET = 1, FSLBM_BUBBLE_ATMOSPHERE = 2 };
 
 typedef struct {
   int32_t nx, ny, nz;
@@ -119,6 +123,13 @@ typedef struct {
                              65536))); more interface cells in a step is
                              FSLBM_ECAPACITY */
   int32_t pad_;
+  double contact_angle;   /* static contact angle at walls in degrees,
+                             measured in the liquid (Sec. 3.2): a column of
+                             the height-function stencil that lies in a wall
+                             takes the mirrored column's liquid height plus
+                             cot(angle) per wall axis crossed.  0 or 90: the
+                             plain mirror (neutral wetting); else 0 < angle <
+                             180 */
 } fslbm_params;
 
 /* What starts the connected-component labelling of a bubble (Sec. 2.3).
@@ -152,7 +163,7 @@ typedef struct {
 
 typedef struct {
   int32_t id;
-  int32_t flags;     /* FSLBM_BUBBLE_INLET */
+  int32_t flags;     /* FSLBM_BUBBLE_* bits */
   double volume;     /* V: gas cells count 1, interface cells 1 - phi */
   double v_star;     /* V*: gas amount at the reference pressure */
   double pressure;   /* p0 V* / max(V, 1e-2) */

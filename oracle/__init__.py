@@ -40,7 +40,7 @@ class _Params(C.Structure):
                 ("periodic", C.c_int32 * 3), ("collision", C.c_int32), ("freeze_conversions", C.c_int32),
                 ("tau", C.c_double), ("trt_lambda", C.c_double), ("sigma", C.c_double),
                 ("g", C.c_double * 3), ("p0", C.c_double), ("eps", C.c_double),
-                ("inject_rate", C.c_double)]
+                ("inject_rate", C.c_double), ("contact_angle", C.c_double)]
 
 
 _lib = None
@@ -99,6 +99,7 @@ def make_params(d: dict) -> _Params:
     p.p0 = float(d.get("p0", 1.0 / 3.0))
     p.eps = float(d.get("eps_convert", d.get("eps", 1e-2)))
     p.inject_rate = float(d.get("inject_rate", 0.0))
+    p.contact_angle = float(d.get("contact_angle", 0.0))
     return p
 
 

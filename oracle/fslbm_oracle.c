@@ -327,16 +327,54 @@ static void youngs_normal(const orc *o, const double *phi, const uint8_t *type, 
  * it) must not depend on round-off. */
 #define TIE_REL 1e-10
 
+/* cot of the static contact angle: 0 for the neutral angle (90 degrees,
+ * also selected by 0) so that the wall rule is then exactly the mirror. */
+static double wall_cot(const orc_params *p) {
+  double t = p->contact_angle;
+  if (t == 0.0 || t == 90.0) return 0.0;
+  double r = t * (3.14159265358979323846 / 180.0);
+  return cos(r) / sin(r);
+}
+
+/* Number of footprint axes (e1, e2) along which the column through
+ * footprint cell c (its own position along d) lies in a wall: the cell is a
+ * wall (or outside the box) and the coordinate is on a face layer of a
+ * non-periodic axis. */
+static int ghost_axes(const orc *o, const uint8_t *type, const int *c, int e1, int e2) {
+  int n[3] = {o->P.nx, o->P.ny, o->P.nz};
+  int w[3];
+  int inside = 1;
+  for (int k = 0; k < 3; ++k) {
+    w[k] = wrap(c[k], n[k], o->P.periodic[k]);
+    if (w[k] < 0 || w[k] >= n[k]) inside = 0;
+  }
+  if (inside && type[cell_index(o, w[0], w[1], w[2])] != ORC_W) return 0;
+  int m = 0;
+  if (!o->P.periodic[e1] && (w[e1] <= 0 || w[e1] >= n[e1] - 1)) ++m;
+  if (!o->P.periodic[e2] && (w[e2] <= 0 || w[e2] >= n[e2] - 1)) ++m;
+  return m;
+}
+
 /* Height-function curvature using columns along axis d: columns of 7 fill
  * levels over the 3x3 footprint in the plane of the other two axes give
  * liquid heights H(a,b); kappa follows from their first and second central
  * differences.  kappa > 0 where the liquid is convex (a droplet), < 0 for a
  * bubble; the formula holds for liquid on either side since H counts
- * liquid. */
+ * liquid.
+ * Wetting (Sec. 3.2; the paper's model is in a reference that is not
+ * available): a column whose footprint lies in a wall is a ghost column.
+ * Where the interface meets the wall at the static angle theta (measured in
+ * the liquid), the liquid height of a column parallel to the wall grows by
+ * cot(theta) per cell towards the wall, whichever side the liquid is on, so
+ * the ghost column takes the mirrored column's height plus cot(theta) per
+ * wall axis crossed (ghost heights from the contact angle, as in height-
+ * function contact-angle methods for VOF).  theta = 90 degrees leaves the
+ * mirror. */
 static double height_curvature_axis(const orc *o, const double *phi, const uint8_t *type, int x,
                                     int y, int z, int d) {
   int e1 = (d == 0) ? 1 : 0;
   int e2 = (d == 2) ? 1 : 2;
+  const double cot = wall_cot(&o->P);
   double H[3][3];
   for (int a = -1; a <= 1; ++a)
     for (int b = -1; b <= 1; ++b) {
@@ -347,6 +385,13 @@ static double height_curvature_axis(const orc *o, const double *phi, const uint8
         c[e2] += b;
         c[d] += k;
         s += phi_sample(o, phi, type, c[0], c[1], c[2]);
+      }
+      if (cot != 0.0) {
+        int c[3] = {x, y, z};
+        c[e1] += a;
+        c[e2] += b;
+        const int m = ghost_axes(o, type, c, e1, e2);
+        if (m) s += m * cot;
       }
       H[a + 1][b + 1] = s;
     }
@@ -433,8 +478,9 @@ static double cell_gas_volume(uint8_t t, double phi) {
 }
 
 /* Ideal-gas pressure (Sec. 2.2): p = V* / V p0; the volume is floored at
- * 1e-2 for vanishing bubbles. */
-static double bubble_pressure(double p0, double vstar, double vol) {
+ * 1e-2 for vanishing bubbles.  An atmosphere bubble stays at p0. */
+static double bubble_pressure(double p0, int32_t flags, double vstar, double vol) {
+  if (flags & ORC_BUBBLE_ATMOSPHERE) return p0;
   double v = vol > 1e-2 ? vol : 1e-2;
   return p0 * vstar / v;
 }
@@ -604,7 +650,7 @@ orc *orc_create(const orc_params *p, const uint8_t *type, const double *phi, con
   free(vacc);
   for (int32_t k = 0; k < nb; ++k) {
     o->b_vstar[k] = b_vstar[k] > 0.0 ? b_vstar[k] : o->b_vol[k] * b_pinit[k] / p->p0;
-    o->b_p[k] = bubble_pressure(p->p0, o->b_vstar[k], o->b_vol[k]);
+    o->b_p[k] = bubble_pressure(p->p0, o->b_flags[k], o->b_vstar[k], o->b_vol[k]);
   }
   o->next_id = next_id0 > maxid ? next_id0 : maxid + 1;
   o->step = step0;
@@ -756,7 +802,7 @@ struct comp {
   int32_t *ids; /* distinct old bubbles (table indices) in the component */
   int32_t nids, cap;
   xsum vol, vstar;
-  int inlet;
+  int inlet, atmosphere;
   int64_t ncell;
 };
 
@@ -781,6 +827,9 @@ static void comp_note(struct comp *c, int32_t b) {
  *    V_b <= 0), i.e. V*_K = sum_b V*_b V(b in K) / V_b.
  * For a pure merge this gives V* = sum V*_b and V = sum V_b (Sec. 2.3.1);
  * for a pure split every daughter keeps the mother's pressure (Sec. 2.3.2).
+ * K owns inlet cells if it holds one, and is an atmosphere if it holds
+ * cells of an atmosphere bubble (a bubble that reaches the open top joins
+ * it and takes its constant pressure).
  * Returns 1 if a new ID was created. */
 static int phase_f(orc *o, const double *old_vol, const int64_t *old_ncell) {
   const int64_t N = o->N;
@@ -814,6 +863,7 @@ static int phase_f(orc *o, const double *old_vol, const int64_t *old_ncell) {
     xsum_add(&c->vstar, old_vol[b] > 0.0 ? ratio[b] * w : o->b_vstar[b] / (double)old_ncell[b]);
     c->ncell += 1;
     if (o->type2[i] == ORC_IN) c->inlet = 1;
+    if (o->b_flags[b] & ORC_BUBBLE_ATMOSPHERE) c->atmosphere = 1;
   }
   /* number of components each old bubble appears in */
   int32_t *ncomp_of = calloc((size_t)(o->nb > 0 ? o->nb : 1), sizeof(int32_t));
@@ -841,7 +891,7 @@ static int phase_f(orc *o, const double *old_vol, const int64_t *old_ncell) {
       nvstar[c] = xsum_value(&K->vstar);
       nvol[c] = xsum_value(&K->vol);
     }
-    nflags[c] = K->inlet ? 1 : 0;
+    nflags[c] = (K->inlet ? ORC_BUBBLE_INLET : 0) | (K->atmosphere ? ORC_BUBBLE_ATMOSPHERE : 0);
     nncell[c] = K->ncell;
   }
   for (int64_t i = 0; i < N; ++i)
@@ -1086,8 +1136,8 @@ static int one_step(orc *o) {
 
   /* Phase G: injection and ideal-gas pressure. */
   for (int32_t b = 0; b < o->nb; ++b) {
-    if (o->b_flags[b] & 1) o->b_vstar[b] += o->P.inject_rate;
-    o->b_p[b] = bubble_pressure(o->P.p0, o->b_vstar[b], o->b_vol[b]);
+    if (o->b_flags[b] & ORC_BUBBLE_INLET) o->b_vstar[b] += o->P.inject_rate;
+    o->b_p[b] = bubble_pressure(o->P.p0, o->b_flags[b], o->b_vstar[b], o->b_vol[b]);
   }
 
   /* commit t+1 */

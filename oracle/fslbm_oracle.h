@@ -32,7 +32,15 @@ typedef struct {
   double p0;           /* reference pressure rho0 cs^2, rho0 = 1 */
   double eps;          /* conversion threshold margin */
   double inject_rate;  /* V* added per step to inlet-owning bubbles */
+  double contact_angle; /* static contact angle at walls in degrees, measured
+                           in the liquid (Sec. 3.2); 0 or 90: neutral (mirror) */
 } orc_params;
+
+/* Bubble flags: bit 0 the bubble owns inlet cells (gas is injected);
+ * bit 1 an "atmosphere" held at the reference pressure p0 whatever its
+ * volume (the open top of the pore case, Sec. 3.2). */
+#define ORC_BUBBLE_INLET 1
+#define ORC_BUBBLE_ATMOSPHERE 2
 
 typedef struct orc orc;
 

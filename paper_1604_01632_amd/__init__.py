@@ -40,7 +40,8 @@ class Params(C.Structure):
                 ("force_topology", C.c_int32), ("freeze_conversions", C.c_int32),
                 ("watchdog_every", C.c_int32), ("watchdog_drift", C.c_double),
                 ("debug_flags", C.c_int32), ("split_trigger", C.c_int32),
-                ("trigger_cos", C.c_double), ("iface_capacity", C.c_int32), ("pad_", C.c_int32)]
+                ("trigger_cos", C.c_double), ("iface_capacity", C.c_int32), ("pad_", C.c_int32),
+                ("contact_angle", C.c_double)]
 
 
 class BubbleInit(C.Structure):
@@ -161,6 +162,7 @@ def make_params(d: dict) -> Params:
     p.split_trigger = int(d.get("split_trigger", TRIGGER_EXACT))
     p.trigger_cos = float(d.get("trigger_cos", -0.5))
     p.iface_capacity = int(d.get("iface_capacity", 0))
+    p.contact_angle = float(d.get("contact_angle", 0.0))
     return p
 
 

@@ -136,7 +136,18 @@ const char *check_params(const fslbm_params *p) {
     return "unknown split_trigger";
   if (p->split_trigger == FSLBM_TRIGGER_NORMALS && !(p->trigger_cos >= -1.0 && p->trigger_cos <= 1.0))
     return "trigger_cos must lie in [-1, 1]";
+  if (!(p->contact_angle >= 0.0 && p->contact_angle < 180.0))
+    return "contact_angle must be 0 (neutral) or lie in (0, 180) degrees";
   return nullptr;
+}
+
+// cot of the static contact angle; exactly 0 for the neutral angle (90
+// degrees, or 0 for unset), so that the wall rule is then the mirror.
+double wall_cot(const fslbm_params &p) {
+  const double t = p.contact_angle;
+  if (t == 0.0 || t == 90.0) return 0.0;
+  const double r = t * (3.14159265358979323846 / 180.0);
+  return std::cos(r) / std::sin(r);
 }
 
 // --------------------------------------------------------------- context
@@ -184,6 +195,7 @@ void build_devs(Ctx &c) {
   d.split_trigger = c.P.split_trigger;
   d.icap = (int)iface_capacity(c.P);
   d.trigger_cos = c.P.trigger_cos;
+  d.wall_cot = wall_cot(c.P);
   d.drift_tol = c.P.watchdog_drift;
   d.collision = c.P.collision;
   d.N = c.N;
@@ -726,11 +738,11 @@ int fslbm_create(const fslbm_params *params, const uint8_t *cell_type, const dou
   for (int s = 0; s < n_bubbles; ++s) b_vol[s] = ex_value(&vw[(size_t)s * EX_WORDS]);
   for (int k = 0; k < n_bubbles; ++k) {
     b_id[k] = bubbles[k].id;
-    b_flags[k] = bubbles[k].flags & FSLBM_BUBBLE_INLET;
+    b_flags[k] = bubbles[k].flags & (FSLBM_BUBBLE_INLET | FSLBM_BUBBLE_ATMOSPHERE);
     b_live[k] = 1;
     b_vstar[k] = bubbles[k].v_star > 0.0 ? bubbles[k].v_star : b_vol[k] * bubbles[k].p_init / p.p0;
     const double v = b_vol[k] > 1e-2 ? b_vol[k] : 1e-2;
-    b_p[k] = p.p0 * b_vstar[k] / v;
+    b_p[k] = (b_flags[k] & FSLBM_BUBBLE_ATMOSPHERE) ? p.p0 : p.p0 * b_vstar[k] / v;
   }
 
   // ---- fields

@@ -56,8 +56,13 @@ constexpr int VA_FIX_SCALE = 53;
 constexpr int VA_CNT = EX_WORDS + VA_FIXN;
 constexpr int VACC = EX_WORDS + VA_FIXN + 1;
 // Per-new-component accumulators of a labelling event: exact-sum words of
-// the volume and of V*, then ncells, ngas, niface, inlet cells.
-constexpr int NACC = 2 * EX_WORDS + 4;
+// the volume and of V*, then ncells, ngas, niface, inlet cells, cells of
+// atmosphere bubbles.
+constexpr int NACC = 2 * EX_WORDS + 5;
+
+// Bubble flag bits (as in the C ABI).
+constexpr int BUBBLE_INLET = 1;
+constexpr int BUBBLE_ATMOSPHERE = 2;
 
 struct Scalars {
   long long step;
@@ -103,6 +108,7 @@ struct Dev {
   int split_trigger;  // 0 exact 3x3x3 test, 1 anti-parallel normals
   int icap;           // capacity of the interface list and its per-slot arrays
   double trigger_cos;
+  double wall_cot;   // cot of the static contact angle (0: mirror at walls)
   int collision;
   double drift_tol;  // watchdog: relative total-mass drift bound (<= 0: off)
   long long N;

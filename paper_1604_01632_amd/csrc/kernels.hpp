@@ -610,6 +610,25 @@ __device__ __forceinline__ R height_curvature_cached(const Dev &d, const R *phi,
         else v = W.get(d, phi, ox, oy, oz);
         s += v;
       }
+      // wetting: a column whose footprint lies in a wall takes the
+      // mirrored column's liquid height plus cot(theta) per wall axis
+      // crossed (the liquid height of a column parallel to the wall grows
+      // by cot(theta) per cell towards a wall met at the static contact
+      // angle theta, measured in the liquid)
+      if (d.wall_cot != 0.0) {
+        const uint32_t f1 = DD == 0 ? W.yf : W.xf;
+        const uint32_t f2 = DD == 2 ? W.yf : W.zf;
+        const int m = (int)((f1 >> (a + 3)) & 1u) + (int)((f2 >> (b + 3)) & 1u);
+        if (m) {
+          const int ox = DD == 0 ? 0 : a;
+          const int oy = DD == 0 ? a : (DD == 1 ? 0 : b);
+          const int oz = DD == 2 ? 0 : b;
+          const int cx = W.xp[ox + 3], cy = W.yp[oy + 3], cz = W.zp[oz + 3];
+          const bool in = cx >= 0 && cx < d.nx && cy >= 0 && cy < d.ny && cz >= 0 && cz < d.nz;
+          if (!in || (d.flag_src[cx + d.nx * (cy + d.ny * cz)] & TYPE_MASK) == T_WALL)
+            s += (R)m * (R)d.wall_cot;
+        }
+      }
       H[a + 1][b + 1] = s;
     }
   const R Ha = (R)0.5 * (H[2][1] - H[0][1]);
@@ -2167,6 +2186,7 @@ struct K_label_accumulate {
       const int sl = d.bslot[i];
       const int a2 = d.aux2[r], a0 = d.aux0[r];
       const double rt = d.b_ratio[sl];
+      const int bfl = d.b_flags[sl];
       if (ok && (a2 & 2)) {
         key = a0;
         const double w = t == T_IFACE ? 1.0 - (double)ph : 1.0;
@@ -2182,6 +2202,7 @@ struct K_label_accumulate {
         v[2 * EX_WORDS + 1] = (t == T_GAS || t == T_INLET) ? 1 : 0;
         v[2 * EX_WORDS + 2] = t == T_IFACE ? 1 : 0;
         v[2 * EX_WORDS + 3] = t == T_INLET ? 1 : 0;
+        v[2 * EX_WORDS + 4] = (bfl & BUBBLE_ATMOSPHERE) ? 1 : 0;
         d.bslot[i] = d.newslot[key];
       }
       d.lab[i] = -1;
@@ -2204,7 +2225,8 @@ __device__ __forceinline__ void install_one(const Dev &d, int k, const unsigned 
     wv[c] = ll(a[c]);
     ws[c] = ll(a[EX_WORDS + c]);
   }
-  d.b_flags[s] = ll(a[2 * EX_WORDS + 3]) > 0 ? 1 : 0;
+  d.b_flags[s] = (ll(a[2 * EX_WORDS + 3]) > 0 ? BUBBLE_INLET : 0) |
+                 (ll(a[2 * EX_WORDS + 4]) > 0 ? BUBBLE_ATMOSPHERE : 0);
   d.b_vol[s] = ex_value(wv);
   d.b_vstar[s] = ex_value(ws);
   d.b_ngas[s] = ll(a[2 * EX_WORDS + 1]);
@@ -2269,9 +2291,11 @@ struct K_bubbles {
   for (int s = threadIdx.x; s < d.max_bubbles; s += blockDim.x) {
     d.b_affect[s] = 0;
     if (!d.b_live[s]) continue;
-    if (d.b_flags[s] & 1) d.b_vstar[s] += d.inject;
+    const int fl = d.b_flags[s];
+    if (fl & BUBBLE_INLET) d.b_vstar[s] += d.inject;
     const double v = d.b_vol[s] > 1e-2 ? d.b_vol[s] : 1e-2;
-    d.b_p[s] = d.p0 * d.b_vstar[s] / v;
+    // an atmosphere (open top) stays at the reference pressure
+    d.b_p[s] = (fl & BUBBLE_ATMOSPHERE) ? d.p0 : d.p0 * d.b_vstar[s] / v;
     atomicAdd(&live, 1);
   }
   __syncthreads();

@@ -26,6 +26,7 @@ import numpy as np
 
 GAS, IFACE, LIQ, WALL, INLET = 0, 1, 2, 3, 4
 BUBBLE_INLET = 1  # bubble flag bit: the bubble owns inlet cells
+BUBBLE_ATMOSPHERE = 2  # bubble flag bit: constant pressure p0 (open top)
 
 P0 = 1.0 / 3.0  # reference pressure rho0 * cs^2 with rho0 = 1 (Sec. 2.2)
 
@@ -50,12 +51,16 @@ class Scene:
     bubbles: list  # [(id, flags, v_star, p_init)]; v_star <= 0: derive from p_init
     steps: int = 0  # horizon the scene is meant for
     meta: dict = field(default_factory=dict)
+    contact_angle: float = 0.0  # static contact angle at walls, degrees (0: neutral)
+    collision: int = 0  # 0 BGK, 1 TRT (the default of params())
 
     @property
     def n(self) -> int:
         return self.nx * self.ny * self.nz
 
-    def params(self, precision: int = 0, collision: int = 0, **over) -> dict:
+    def params(self, precision: int = 0, collision: int = None, **over) -> dict:
+        if collision is None:
+            collision = self.collision
         d = dict(
             nx=self.nx, ny=self.ny, nz=self.nz, periodic=tuple(self.periodic),
             precision=precision, collision=collision, tau=self.tau,
@@ -63,6 +68,7 @@ class Scene:
             eps_convert=self.eps, inject_rate=self.inject_rate,
             max_bubbles=1024, force_topology=0, freeze_conversions=0, watchdog_every=0,
             watchdog_drift=0.0, debug_flags=0, split_trigger=0, trigger_cos=-0.5, iface_capacity=0,
+            contact_angle=self.contact_angle,
         )
         d.update(over)
         return d
@@ -402,6 +408,134 @@ def orifice(n=(128, 128, 256), r=6.0, g=1e-5, tau=0.6, sigma=2e-3, Q=0.05, steps
     return _finish(name, nx, ny, nz, (0, 0, 0), phi, fixed, rho, tau, sigma, (0.0, 0.0, -g), 1e-2,
                    Q, lambda px, py, pz: np.zeros(px.shape, dtype=np.int64), lambda b: p_in,
                    steps, meta=dict(r=r))
+
+
+def wall_cap(theta, n=28, M=16, R=7.0, sigma=1e-3, tau=0.6, contact_angle=None, name="wall_cap"):
+    """A gas cap on the low z wall of an n x n x (M + 2) box (x, y periodic,
+    wall layers at z = 0 and z = M + 1): the part above the wall plane of a
+    sphere of radius R whose centre lies R cos(theta) above that plane, so
+    that it meets the wall at theta measured in the liquid.  The liquid is
+    at the Laplace density of the sphere; contact_angle defaults to theta."""
+    h = R * math.cos(math.radians(theta))
+    free = spheres(n=(n, n, 2 * M), centers=((n / 2.0, n / 2.0, M + h),), radii=(R,), sigma=sigma,
+                   rho_l=1.0 - 6.0 * sigma / R, tau=tau)
+    nzw = M + 2
+    t3 = free.cell_type.reshape(2 * M, n, n)
+    p3 = free.phi.reshape(2 * M, n, n)
+    b3 = free.bubble_id.reshape(2 * M, n, n)
+    r3 = free.rho.reshape(2 * M, n, n)
+    tw = np.full((nzw, n, n), WALL, np.uint8)
+    pw = np.zeros((nzw, n, n))
+    bw = np.full((nzw, n, n), -1, np.int32)
+    rw = np.ones((nzw, n, n))
+    tw[1:M + 1], pw[1:M + 1], bw[1:M + 1], rw[1:M + 1] = t3[M:], p3[M:], b3[M:], r3[M:]
+    N = tw.size
+    return Scene(name, n, n, nzw, (1, 1, 0), tau, sigma, (0.0, 0.0, 0.0), 1e-2, 0.0,
+                 tw.ravel(), pw.ravel(), rw.ravel(), np.zeros(3 * N), bw.ravel(), free.bubbles,
+                 200, dict(theta=theta, R=R),
+                 contact_angle=float(theta if contact_angle is None else contact_angle))
+
+
+# Water-air at 20 C for the pore case (Sec. 3.2 gives rho, eta and g; the
+# surface tension of water against air is not stated there and is taken as
+# 0.0728 N/m).
+WATER_RHO = 998.12       # kg/m^3
+WATER_ETA = 1.002e-3     # Pa s
+WATER_SIGMA = 0.0728     # N/m
+GRAVITY = 9.81           # m/s^2
+PORE_RADIUS = 1.0e-3     # m
+
+
+def pore_units(r_cells, tau):
+    """Lattice units of the pore case: the orifice radius (1 mm) spans
+    r_cells cells; tau fixes the time step through the viscosity,
+    nu_lattice = (tau - 1/2) / 3 = nu dt / dx^2; densities are scaled by the
+    water density (lattice rho = 1), so g, sigma and a volume flow map by
+    g dt^2 / dx, sigma dt^2 / (rho dx^3) and Q dt / dx^3."""
+    dx = PORE_RADIUS / r_cells
+    nu = WATER_ETA / WATER_RHO
+    nu_l = (tau - 0.5) / 3.0
+    dt = nu_l * dx * dx / nu
+    return dict(dx=dx, dt=dt, nu_lattice=nu_l, g=GRAVITY * dt * dt / dx,
+                sigma=WATER_SIGMA * dt * dt / (WATER_RHO * dx ** 3),
+                q_per_ml_min=(1e-6 / 60.0) * dt / dx ** 3, mm3_per_cell=(dx * 1e3) ** 3)
+
+
+def pore_units_similar(r_cells, sigma=0.002, tau=0.6):
+    """Lattice units of the pore case by similarity instead of a physical
+    time step: the Bond number rho g R^2 / sigma of water-air at the 1 mm
+    orifice and the flow rate in units of R^3 per capillary time
+    sqrt(rho R^3 / sigma) are kept, sigma and tau are free (the viscosity is
+    not matched: in the quasi-static limit of Sec. 3.2 it does not set the
+    detachment volume).  Volumes map by (1 mm / r_cells)^3."""
+    R = PORE_RADIUS
+    bond = WATER_RHO * GRAVITY * R * R / WATER_SIGMA
+    tc = math.sqrt(WATER_RHO * R ** 3 / WATER_SIGMA)          # s
+    tc_l = math.sqrt(float(r_cells) ** 3 / sigma)            # steps
+    q_star = (1e-6 / 60.0) / (R ** 3 / tc)                   # 1 ml/min in R^3 per tc
+    dx = R / r_cells
+    return dict(dx=dx, dt=tc / tc_l, nu_lattice=(tau - 0.5) / 3.0, g=bond * sigma / r_cells ** 2,
+                sigma=sigma, q_per_ml_min=q_star * r_cells ** 3 / tc_l,
+                mm3_per_cell=(dx * 1e3) ** 3, bond=bond, capillary_time_steps=tc_l)
+
+
+def pore(r=20, theta=70.0, q_ml_min=1.0, tau=0.503, top_gas=None, n=None, collision=0,
+         units=None, cap=0.5, steps=0, name="pore"):
+    """The pore case (Sec. 3.2) in lattice units: a box of 7.6 r x 7.6 r x
+    15 r cells (228 x 228 x 450 at r = 30) with wall layers on every face;
+    the bottom wall is pierced by a disk of inlet cells of radius r, through
+    which gas enters at q_ml_min; the top is open: the liquid surface lies
+    top_gas cells (default 3 r) below the top wall and the gas above it is an
+    atmosphere bubble held at p0.  The bubble starts as a spherical cap of height
+    cap * r over the pore (its rim on the pore's edge) at the Laplace
+    pressure over the hydrostatic liquid, which has p0 at its surface.
+    Static contact angle theta at the walls; BGK collision by default.
+    units: the pore_units mapping (default from r and tau); n overrides the
+    box size."""
+    u = units or pore_units(r, tau)
+    if n is None:
+        n = (int(round(7.6 * r)), int(round(7.6 * r)), 15 * r)
+    if top_gas is None:
+        top_gas = 3 * r  # room for the liquid the bubble displaces
+    nx, ny, nz = n
+    g, sigma = u["g"], u["sigma"]
+    zs = nz - 1 - top_gas  # first gas layer of the atmosphere
+    cx, cy = nx / 2.0, ny / 2.0
+    h0 = cap * r
+    Rs = (r * r + h0 * h0) / (2.0 * h0)  # sphere through the pore's rim
+    zc = 1.0 + h0 - Rs                   # its centre (the wall plane is z = 1)
+    hh = math.sqrt(3.0) / 2.0 + 1e-9
+
+    def gas_fn(px, py, pz):
+        d2 = (px - cx) ** 2 + (py - cy) ** 2 + (pz - zc) ** 2
+        return (d2 < Rs * Rs) | (pz >= zs - 0.5)
+
+    def band_fn(xc, yc, zc_):
+        d = np.sqrt((xc - cx) ** 2 + (yc - cy) ** 2 + (zc_ - zc) ** 2)
+        out = np.where(d + hh < Rs, 1, np.where(np.abs(d - Rs) <= hh, 0, -1))
+        out = np.where(zc_ >= zs + 0.5, 1, np.where(np.abs(zc_ - (zs - 0.5)) < 1.0, 0, out))
+        return out.astype(np.int8)
+
+    frac = _gas_fraction(nx, ny, nz, gas_fn, band_fn, 8)
+    x, y, z = _grid(nx, ny, nz)
+    phi = 1.0 - frac
+    disk = (x + 0.5 - cx) ** 2 + (y + 0.5 - cy) ** 2 <= float(r) * float(r)
+    face = (x == 0) | (x == nx - 1) | (y == 0) | (y == ny - 1) | (z == 0) | (z == nz - 1)
+    fixed = np.full(nx * ny * nz, 255, dtype=np.uint8)
+    fixed[face] = WALL
+    fixed[(z == 0) & disk & ~((x == 0) | (x == nx - 1) | (y == 0) | (y == ny - 1))] = INLET
+    # hydrostatic: p = p0 at the surface (the atmosphere's pressure)
+    rho = 1.0 + 3.0 * g * ((zs - 0.5) - z)
+    p_in = (1.0 + 3.0 * g * ((zs - 0.5) - 1.0)) / 3.0 + 2.0 * sigma / Rs
+    sc = _finish(name, nx, ny, nz, (0, 0, 0), phi, fixed, rho, tau, sigma, (0.0, 0.0, -g),
+                 1e-2, q_ml_min * u["q_per_ml_min"],
+                 lambda px, py, pz: (pz >= zs - 1.5).astype(np.int64),
+                 lambda b: P0 if b == 1 else p_in, steps,
+                 meta=dict(r=r, theta=theta, q_ml_min=q_ml_min, units=u, surface=zs - 0.5))
+    sc.bubbles = [(b, f | (BUBBLE_ATMOSPHERE if b == 1 else 0), v, p) for b, f, v, p in sc.bubbles]
+    sc.contact_angle = float(theta)
+    sc.collision = int(collision)
+    return sc
 
 
 # ------------------------------------------------------ named configurations
