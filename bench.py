@@ -304,9 +304,12 @@ def bench_forms(args) -> int:
     torch.cuda.set_device(0)
     forms = ("fp64", "fp32", "fp16dev")
     sc = scenes.config("p1")
+    start = args.start_step if args.start_step >= 0 else RUPTURE_START
     speed = {}
     for prec in forms:
         dom = F.Domain.from_scene(sc, prec)
+        if start:
+            dom.step(start)  # into the rupture epoch, as the default line
         dom.step(args.warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -359,7 +362,8 @@ def bench_forms(args) -> int:
         "ms_per_step": speed["fp32"]["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "precision forms: p1 256^3 thread rupture in fp64, fp32 and "
-                               "fp16-deviation storage (value: fp32); accuracy of fp32 and "
+                               f"fp16-deviation storage, window after step {start} + "
+                               f"{args.warmup} (value: fp32); accuracy of fp32 and "
                                "fp16dev against fp64 at the c2, c3 and c3d (detaching orifice) "
                                "horizons, bubbles paired by centroid",
                    "p1": speed,
