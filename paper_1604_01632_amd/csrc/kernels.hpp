@@ -650,6 +650,7 @@ __device__ __forceinline__ R height_curvature_cached(const Dev &d, const R *phi,
 template <class P>
 struct K_geom {
   static constexpr int THREADS = 256;
+  static constexpr int MIN_WAVES = P::EXACT ? 1 : 4;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   using R = typename P::R;
   const R *phi = (const R *)d.phi_src;
