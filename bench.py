@@ -63,7 +63,7 @@ def count_types(t) -> dict:
 
 def host_threads() -> int:
     """Host threads this job may use: the OpenMP setting of the host (the
-    GPU machine gives each GPU a share of its cores), else the CPUs of this
+    host may give each GPU a share of its cores), else the CPUs of this
     process's affinity mask."""
     env = os.environ.get("OMP_NUM_THREADS", "")
     if env.isdigit() and int(env) > 0:
