@@ -30,6 +30,9 @@ def _scenes():
         scenes.config("c1"),
         scenes.merge_ids_if_touching(scenes.random_blobs(n=(16, 20, 18), nblob=3, seed=3, sigma=1e-2)),
         scenes.orifice(n=(16, 16, 20), r=3.0, g=1e-5, Q=0.05),
+        # wetting at 70 degrees and an atmosphere at the top
+        scenes.pore(r=3, n=(20, 20, 32), tau=0.6, top_gas=5, theta=70.0, q_ml_min=1.0,
+                    units=dict(g=2e-4, sigma=2e-3, q_per_ml_min=0.05)),
         scenes.batch_domains(count=1, seed=11, extents=(32, 48))[0],
     ]
 
@@ -88,7 +91,7 @@ def test_batch_fp64_matches_oracle():
     import oracle
     from paper_1604_01632_amd import Batch, Domain
 
-    scs = _scenes()[:5]
+    scs = _scenes()[:6]
     doms = [Domain.from_scene(sc, "fp64") for sc in scs]
     orcs = [oracle.Oracle.from_scene(sc) for sc in scs]
     b = Batch(doms)
