@@ -479,7 +479,7 @@ def pore_units_similar(r_cells, sigma=0.002, tau=0.6):
                 mm3_per_cell=(dx * 1e3) ** 3, bond=bond, capillary_time_steps=tc_l)
 
 
-def pore(r=20, theta=70.0, q_ml_min=1.0, tau=0.503, top_gas=None, n=None, collision=0,
+def pore(r=20, theta=70.0, q_ml_min=1.0, tau=0.6, top_gas=None, n=None, collision=0,
          units=None, cap=0.5, steps=0, name="pore"):
     """The pore case (Sec. 3.2) in lattice units: a box of 7.6 r x 7.6 r x
     15 r cells (228 x 228 x 450 at r = 30) with wall layers on every face;
@@ -490,9 +490,11 @@ def pore(r=20, theta=70.0, q_ml_min=1.0, tau=0.503, top_gas=None, n=None, collis
     cap * r over the pore (its rim on the pore's edge) at the Laplace
     pressure over the hydrostatic liquid, which has p0 at its surface.
     Static contact angle theta at the walls; BGK collision by default.
-    units: the pore_units mapping (default from r and tau); n overrides the
-    box size."""
-    u = units or pore_units(r, tau)
+    units: a lattice mapping, by default pore_units_similar(r, tau=tau)
+    (pore_units, the physical time step of water-air, gives lattice
+    surface tensions this method does not run stably at affordable tau);
+    n overrides the box size."""
+    u = units or pore_units_similar(r, tau=tau)
     if n is None:
         n = (int(round(7.6 * r)), int(round(7.6 * r)), 15 * r)
     if top_gas is None:
