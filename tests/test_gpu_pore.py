@@ -110,3 +110,28 @@ def test_detachment_trend_and_rise_into_the_atmosphere():
     # Table tab:detRad: a smaller detachment volume at 70 than at 90 degrees
     assert v70 < 0.85 * v90
     assert t70 < t90
+
+
+def test_pore_checkpoint_restart():
+    """Inlet, atmosphere and wetting through a checkpoint: 200 steps
+    straight equal 100 steps, a readout through the boundary, a new domain
+    from it and 100 more steps, bit for bit (FP64)."""
+    from paper_1604_01632_amd import Domain
+    sc = _mini_pore()
+    a = Domain.from_scene(sc, "fp64")
+    a.step(200)
+    c = Domain.from_scene(sc, "fp64")
+    c.step(100)
+    ck = c.read()
+    bub = c.bubbles()
+    assert sorted(int(f) for f in bub["flags"]) == [BUBBLE_INLET, BUBBLE_ATMOSPHERE]
+    binit = [(int(i), int(f), float(v), 0.0) for i, f, v in zip(bub["id"], bub["flags"], bub["v_star"])]
+    d = Domain(sc.params(precision=0), ck["cell_type"], ck["phi"], ck["rho"], ck["u"], ck["bubble_id"],
+               binit, f_init=ck["f"], restore=ck["scalars"], mass_init=ck["mass"])
+    d.step(100)
+    ra, rd = a.read(), d.read()
+    for key in ("cell_type", "bubble_id", "phi", "mass", "f"):
+        assert np.array_equal(ra[key], rd[key]), key
+    ba, bd = a.bubbles(), d.bubbles()
+    for key in ba:
+        assert np.array_equal(ba[key], bd[key]), key
