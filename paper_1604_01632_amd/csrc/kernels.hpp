@@ -1828,7 +1828,7 @@ __device__ __forceinline__ void uf_union(int32_t *lab, int a, int b) {
 //
 // Labelled set, tile by tile (LTILE consecutive cells, 16 per thread): the
 // cells of the set are listed (one atomic per tile) and labelled with the
-// first cell of their x-run inside the tile.  Cells outside the set hold
+// first cell of their x-run inside the wave's cells.  Cells outside the set hold
 // -1 (filled at creation, restored by k_label_accumulate).
 struct K_label_init {
   static constexpr int THREADS = 256;
@@ -1881,18 +1881,17 @@ struct K_label_init {
     // the whole tile outside the set: nothing to do
     if (!__syncthreads_or(bits != 0u)) continue;
     // initial local labels: the first cell of the cell's x-run inside the
-    // tile, so that every row segment starts as a star (depth one).  A run
-    // starts at a set cell that is the tile's first, at x = 0, or after a
-    // cell outside the set; the run that enters a thread's cells from the
-    // left started at the last start of the threads before it (a max-scan
-    // over the block).
+    // wave's 1024 cells, so that every row segment starts as a star (depth
+    // one).  A run starts at a set cell that is the wave's first, at x = 0,
+    // or after a cell outside the set; the run that enters a thread's cells
+    // from the left started at the last start of the lanes before it (a
+    // max-scan over the wave).  A run cut at a wave boundary (only where
+    // the row length does not divide 1024) is joined by the union pass
+    // through its +x edge.
     {
-      __shared__ uint32_t wbits[4];
-      if (lane == 63) wbits[w] = bits;
-      __syncthreads();
       uint32_t pb = __shfl_up(bits, 1, 64);
-      if (lane == 0) pb = w > 0 ? wbits[w - 1] : 0u;
-      const bool left = threadIdx.x > 0 && ((pb >> 15) & 1u);  // the cell before is set
+      if (lane == 0) pb = 0u;
+      const bool left = lane > 0 && ((pb >> 15) & 1u);  // the cell before is set
       const int x0 = (int)(i0 % d.nx);
       int last = -1;
       {
@@ -1910,12 +1909,8 @@ struct K_label_init {
         const int v = __shfl_up(incl, off, 64);
         if (lane >= off && v > incl) incl = v;
       }
-      if (lane == 63) wsum[w] = incl;
-      __syncthreads();
       int carry = __shfl_up(incl, 1, 64);
       if (lane == 0) carry = -1;
-      for (int k = 0; k < w; ++k) carry = wsum[k] > carry ? wsum[k] : carry;
-      __syncthreads();
       int start = (left && x0 != 0) ? carry : -1;
       int x = x0;
 #pragma unroll
@@ -2003,6 +1998,25 @@ struct K_label_union {
       const int a = 2 * q + 1;
       const long long j = ok ? nbr_checked(d, x, y, z, CX[a], CY[a], CZ[a]) : -1;
       ln[q] = j >= 0 ? d.lab[j] : -1;
+    }
+    // a diagonal edge is implied when one of the two cells beside it (one
+    // unit step along either of its axes) is in the set: the two unit
+    // edges through that cell are united by their own cells (unit edges
+    // are never skipped).  Directions 1, 3, 5 are +x, +y, +z; 7 +x+y,
+    // 9 +x-y, 11 +x+z, 13 +x-z, 15 +y+z, 17 +y-z; of the cells beside a
+    // diagonal, the +x, +y, +z ones are those read above.
+    static_assert(CX[1] == 1 && CY[3] == 1 && CZ[5] == 1 && CX[7] == 1 && CY[7] == 1 &&
+                      CX[9] == 1 && CY[9] == -1 && CX[11] == 1 && CZ[11] == 1 && CX[13] == 1 &&
+                      CZ[13] == -1 && CY[15] == 1 && CZ[15] == 1 && CY[17] == 1 && CZ[17] == -1,
+                  "direction order of the diagonal rule");
+    {
+      const bool sx = ln[0] >= 0, sy = ln[1] >= 0, sz = ln[2] >= 0;
+      if (sx || sy) ln[3] = -1;
+      if (sx) ln[4] = -1;
+      if (sx || sz) ln[5] = -1;
+      if (sx) ln[6] = -1;
+      if (sy || sz) ln[7] = -1;
+      if (sy) ln[8] = -1;
     }
 #pragma unroll
     for (int q = 0; q < Q / 2; ++q) {
