@@ -135,3 +135,30 @@ def test_pore_checkpoint_restart():
     ba, bd = a.bubbles(), d.bubbles()
     for key in ba:
         assert np.array_equal(ba[key], bd[key]), key
+
+
+def test_cap_relaxes_to_its_contact_angle():
+    """A hemispherical gas cap (90 degrees) on a wall whose contact angle
+    is 60, 90 or 120 degrees: the base contracts, stays, or spreads, to the
+    base radius of the spherical cap of the same volume at that angle,
+    a = Rs sin(theta) with V = pi Rs^3 (1 + cos)^2 (2 - cos) / 3, measured
+    as the gas-region cells of the first fluid layer (an interface band of
+    about half a cell beyond the contact line)."""
+    from paper_1604_01632_amd import Domain
+    radii = {}
+    for ang in (60.0, 90.0, 120.0):
+        sc = scenes.wall_cap(90.0, n=40, M=20, R=9.0, sigma=5e-3, contact_angle=ang)
+        d = Domain.from_scene(sc, "fp32")
+        d.step(3000)
+        t = d.read(("cell_type",))["cell_type"].reshape(sc.nz, sc.ny, sc.nx)
+        n = np.count_nonzero((t[1] == GAS) | (t[1] == IFACE))
+        v = float(d.bubbles()["volume"][0])
+        c = np.cos(np.radians(ang))
+        rs = (3.0 * v / (np.pi * (1.0 + c) ** 2 * (2.0 - c))) ** (1.0 / 3.0)
+        a = rs * np.sin(np.radians(ang))
+        radii[ang] = (np.sqrt(n / np.pi), a)
+        d.close()
+    say(f"[pore] cap base radius (measured, cap of the same volume): {radii}")
+    assert radii[60.0][0] < radii[90.0][0] < radii[120.0][0]
+    for ang, (meas, exp) in radii.items():
+        assert abs(meas - (exp + 0.5)) < 1.0, (ang, meas, exp)
