@@ -1827,13 +1827,17 @@ __device__ __forceinline__ void uf_union(int32_t *lab, int a, int b) {
 // cells of more than one bubble.
 //
 // Labelled set, tile by tile (LTILE consecutive cells, 16 per thread): the
-// cells of the set are listed (one atomic per tile) and labelled with the
-// first cell of their x-run inside the wave's cells.  Cells outside the set hold
-// -1 (filled at creation, restored by k_label_accumulate).
+// cells of the set are labelled with the first cell of their x-run inside
+// the wave's cells, and listed in cell order.  A block takes a contiguous
+// range of tiles and appends the set cells of GROUP tiles at a time with one
+// atomic: the appends of all blocks serialise on the one counter.  Cells
+// outside the set hold -1 (filled at creation, restored by
+// k_label_accumulate).
 struct K_label_init {
   static constexpr int THREADS = 256;
+  static constexpr int GROUP = 4;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
-  __shared__ int wsum[4];
+  __shared__ int wsum[GROUP][THREADS / 64];
   __shared__ int base_sh;
   __shared__ int loc[LTILE];
   bubble_volumes(d, bk);
@@ -1841,9 +1845,28 @@ struct K_label_init {
   if (!run) return;
   const bool all = run >= 2;
   const int ntiles = (int)((d.N + LTILE - 1) / LTILE);
+  const int per = (ntiles + bk.n - 1) / bk.n;
+  const int tb = bk.id * per < ntiles ? bk.id * per : ntiles;
+  const int te = tb + per < ntiles ? tb + per : ntiles;
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
   const int lb = 16 * (int)threadIdx.x;  // local index of the thread's first cell
-  for (int tile = bk.id; tile < ntiles; tile += bk.n) {
+  for (int gt = tb; gt < te; gt += GROUP) {  // uniform per block
+  // per tile of the group: the thread's set cells and how many set cells
+  // the lanes before it in its wave hold
+  uint32_t gbits[GROUP];
+  int gpre[GROUP];
+#pragma unroll
+  for (int u = 0; u < GROUP; ++u) {
+    gbits[u] = 0u;
+    gpre[u] = 0;
+  }
+#pragma unroll
+  for (int u = 0; u < GROUP; ++u) {
+    const int tile = gt + u;
+    if (tile >= te) {
+      if (lane == 63) wsum[u][w] = 0;
+      continue;
+    }
     const long long t0 = (long long)tile * LTILE;
     const long long i0 = t0 + lb;
     uint32_t bits = 0;
@@ -1879,7 +1902,10 @@ struct K_label_init {
       }
     }
     // the whole tile outside the set: nothing to do
-    if (!__syncthreads_or(bits != 0u)) continue;
+    if (!__syncthreads_or(bits != 0u)) {
+      if (lane == 63) wsum[u][w] = 0;
+      continue;
+    }
     // initial local labels: the first cell of the cell's x-run inside the
     // wave's 1024 cells, so that every row segment starts as a star (depth
     // one).  A run starts at a set cell that is the wave's first, at x = 0,
@@ -1937,7 +1963,7 @@ struct K_label_init {
       d.lab[i] = (int)(t0 + p);
       d.aux2[i] = 0;
     }
-    // list the set cells: one atomic per tile, cell order inside the tile
+    // the set cells of the lanes before this one in the wave
     const int c = __popc(bits);
     int incl = c;
 #pragma unroll
@@ -1945,19 +1971,32 @@ struct K_label_init {
       const int v = __shfl_up(incl, off, 64);
       if (lane >= off) incl += v;
     }
-    if (lane == 63) wsum[w] = incl;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-      base_sh = tot ? atomicAdd(&d.sc->n_lab, tot) : 0;
+    if (lane == 63) wsum[u][w] = incl;
+    gbits[u] = bits;
+    gpre[u] = incl - c;
+  }
+  // list the set cells of the group: one atomic, cell order
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int u = 0; u < GROUP; ++u)
+      for (int k = 0; k < THREADS / 64; ++k) tot += wsum[u][k];
+    base_sh = tot ? atomicAdd(&d.sc->n_lab, tot) : 0;
+  }
+  __syncthreads();
+  int pos0 = base_sh;
+#pragma unroll
+  for (int u = 0; u < GROUP; ++u) {
+    int pos = pos0 + gpre[u];
+    for (int k = 0; k < THREADS / 64; ++k) {
+      if (k < w) pos += wsum[u][k];
+      pos0 += wsum[u][k];
     }
-    __syncthreads();
-    int before = 0;
-    for (int k = 0; k < w; ++k) before += wsum[k];
-    int pos = base_sh + before + incl - c;
+    const long long i0 = (long long)(gt + u) * LTILE + lb;
     for (int q = 0; q < 16; ++q)
-      if ((bits >> q) & 1u) d.clist[pos++] = (int)(i0 + q);
-    __syncthreads();
+      if ((gbits[u] >> q) & 1u) d.clist[pos++] = (int)(i0 + q);
+  }
+  __syncthreads();  // wsum and base_sh are taken by the next group
   }
   const long long g0 = (long long)bk.id * blockDim.x + threadIdx.x;
   for (long long t = g0; t < d.max_bubbles; t += (long long)bk.n * blockDim.x) {
