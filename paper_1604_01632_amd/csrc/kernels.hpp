@@ -788,18 +788,6 @@ __device__ __forceinline__ typename P::R gas_pair(typename P::R rho, typename P:
 __device__ __forceinline__ bool cand_filled(uint8_t f) { return (f & CAND_F) && !(f & NEAR_INLET); }
 __device__ __forceinline__ bool cand_capped(uint8_t f) { return (f & CAND_F) && (f & NEAR_INLET); }
 
-// Appends the lanes with pred set to a list; returns each such lane's slot.
-// Every lane of the wave must call it.
-__device__ __forceinline__ int wave_append(bool pred, int *counter) {
-  const unsigned long long m = __ballot(pred);
-  if (!m) return -1;
-  const int lane = __lane_id();
-  const int leader = __ffsll((long long)m) - 1;
-  int base = 0;
-  if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
-  base = __shfl(base, leader, 64);
-  return base + (int)__popcll(m & ((1ull << lane) - 1ull));
-}
 
 // A cell is claimed once per step: one byte of the mark field per cell,
 // its low bit set by the first caller.
@@ -1045,6 +1033,29 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
   return (double)m_new;
 }
 
+// Appends the lanes with pred set to a list with one atomic for the whole
+// block (the appends of all blocks serialise on the one counter); returns
+// each such lane's slot, -1 for the others.  Every thread of the block must
+// call it.
+__device__ __forceinline__ int block_append(bool pred, int *counter) {
+  __shared__ int bw[16];
+  __shared__ int bbase;
+  const unsigned long long m = __ballot(pred);
+  const int lane = __lane_id(), w = (int)threadIdx.x >> 6, nw = ((int)blockDim.x + 63) >> 6;
+  if (lane == 0) bw[w] = (int)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < nw; ++k) t += bw[k];
+    bbase = t ? atomicAdd(counter, t) : 0;
+  }
+  __syncthreads();
+  int pos = bbase + (int)__popcll(m & ((1ull << lane) - 1ull));
+  for (int k = 0; k < w; ++k) pos += bw[k];
+  __syncthreads();  // bw and bbase are taken by the next call
+  return pred ? pos : -1;
+}
+
 // Interface cells of time t (list), one per thread; conversion candidates
 // are appended to the candidate list.  The list of a step is about one
 // round of resident waves, so the FP32/FP16 kernels are held to three waves
@@ -1072,7 +1083,7 @@ struct K_iface {
     }
     // at most one entry per cell and step (the counter is reset at the
     // end of the step); the bound only guards the list
-    const int pos = wave_append(cand, &d.sc->n_cand);
+    const int pos = block_append(cand, &d.sc->n_cand);
     if (cand) {
       if (pos < (int)d.N) d.clist[pos] = (int)i;
       else atomicOr(&d.sc->err, ERR_RANGE);
