@@ -1851,6 +1851,10 @@ struct K_label_init {
   __shared__ int wsum[GROUP][THREADS / 64];
   __shared__ int base_sh;
   __shared__ int loc[LTILE];
+  // per tile of a group: each thread's set cells, and how many set cells
+  // the lanes before it in its wave hold (own entries only: no barrier)
+  __shared__ uint32_t gbits[GROUP][THREADS];
+  __shared__ int gpre[GROUP][THREADS];
   bubble_volumes(d, bk);
   const int run = d.sc->label_run;
   if (!run) return;
@@ -1862,18 +1866,11 @@ struct K_label_init {
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
   const int lb = 16 * (int)threadIdx.x;  // local index of the thread's first cell
   for (int gt = tb; gt < te; gt += GROUP) {  // uniform per block
-  // per tile of the group: the thread's set cells and how many set cells
-  // the lanes before it in its wave hold
-  uint32_t gbits[GROUP];
-  int gpre[GROUP];
-#pragma unroll
-  for (int u = 0; u < GROUP; ++u) {
-    gbits[u] = 0u;
-    gpre[u] = 0;
-  }
-#pragma unroll
+#pragma unroll 1
   for (int u = 0; u < GROUP; ++u) {
     const int tile = gt + u;
+    gbits[u][threadIdx.x] = 0u;
+    gpre[u][threadIdx.x] = 0;
     if (tile >= te) {
       if (lane == 63) wsum[u][w] = 0;
       continue;
@@ -1983,8 +1980,8 @@ struct K_label_init {
       if (lane >= off) incl += v;
     }
     if (lane == 63) wsum[u][w] = incl;
-    gbits[u] = bits;
-    gpre[u] = incl - c;
+    gbits[u][threadIdx.x] = bits;
+    gpre[u][threadIdx.x] = incl - c;
   }
   // list the set cells of the group: one atomic, cell order
   __syncthreads();
@@ -1996,16 +1993,17 @@ struct K_label_init {
   }
   __syncthreads();
   int pos0 = base_sh;
-#pragma unroll
+#pragma unroll 1
   for (int u = 0; u < GROUP; ++u) {
-    int pos = pos0 + gpre[u];
+    int pos = pos0 + gpre[u][threadIdx.x];
     for (int k = 0; k < THREADS / 64; ++k) {
       if (k < w) pos += wsum[u][k];
       pos0 += wsum[u][k];
     }
+    const uint32_t bits = gbits[u][threadIdx.x];
     const long long i0 = (long long)(gt + u) * LTILE + lb;
     for (int q = 0; q < 16; ++q)
-      if ((gbits[u] >> q) & 1u) d.clist[pos++] = (int)(i0 + q);
+      if ((bits >> q) & 1u) d.clist[pos++] = (int)(i0 + q);
   }
   __syncthreads();  // wsum and base_sh are taken by the next group
   }

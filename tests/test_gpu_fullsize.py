@@ -99,6 +99,28 @@ def test_p1_first_step_fp64_matches_oracle_bitwise(p1):
     _free(g, o)
 
 
+@pytest.mark.timeout(900)
+def test_wider_lattice_first_step_fp64_matches_oracle_bitwise():
+    """First step of a 320x256x256 lattice of 20 threads in the FP64 form,
+    bit for bit against the oracle.  The labelling of the whole gas region
+    then spreads 5120 tiles of 4096 cells over 1024 blocks: every block
+    lists the cells of more tiles than one append covers (four), so its
+    second append is a partial group."""
+    from paper_1604_01632_amd import Domain
+    oracle = _oracle()
+    sc = scenes.thread_lattice(n=(320, 256, 256), spacing=64, seed=320, steps=1, name="lattice320")
+    say(f"[fullsize] lattice fp64 step 1: {sc.nx}x{sc.ny}x{sc.nz}")
+    g = Domain.from_scene(sc, "fp64")
+    o = oracle.Oracle.from_scene(sc)
+    o.step(1)
+    g.step(1)
+    compare_state(o, g, "lattice320 fp64 step 1", exact=True)
+    n = len(o.bubbles()["id"])
+    say(f"[fullsize] lattice fp64 step 1: bitwise equal, {n} bubbles")
+    assert n == 20
+    _free(g, o)
+
+
 def _first_topology_step(sc, precision):
     """The first step after the warm-up whose labelling creates bubbles."""
     g = _bench_domain(sc, precision)
