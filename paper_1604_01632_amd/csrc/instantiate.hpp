@@ -40,10 +40,9 @@ static void phase_kernels(int ph, bool with_mass, int bulk_threads, L &&launch) 
       launch.template go<K_conv_init<P>>(G_SMALL);
       break;
     case PH_EXCESS:
-      launch.template go<K_excess<P>>(G_SMALL);
+      launch.template go<K_excess_count<P>>(G_EXCOUNT);
       break;
     case PH_GATHER:
-      launch.template go<K_list_count>(G_TILE);
       launch.template go<K_list_scan>(G_ONE);
       launch.template go<K_list_fill>(G_TILE);
       launch.template go<K_gather<P>>(G_LIST);

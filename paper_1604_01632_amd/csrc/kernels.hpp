@@ -1601,6 +1601,24 @@ struct K_list_count {
 }
 };
 
+// The excess-mass pass and the tile counts of the interface list of t+1 in
+// one launch: the first blocks take the excess pass, one block per tile
+// follows.  The types of t+1 are final once the conversions are applied,
+// and the excess pass only adds the receiver bit to flags, so the counts
+// may run beside it.
+template <class P>
+struct K_excess_count {
+  static constexpr int THREADS = 256;
+  static_assert(K_excess<P>::THREADS == THREADS && K_list_count::THREADS == THREADS,
+                "one block size for both parts");
+  static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
+  const int ntiles = (int)((d.N + LTILE - 1) / LTILE);
+  const int nex = bk.n - ntiles;
+  if (bk.id < nex) K_excess<P>::run(d, Blk{bk.id, nex});
+  else K_list_count::run(d, Blk{bk.id - nex, ntiles});
+}
+};
+
 // Single block: exclusive scan of the tile counts.
 struct K_list_scan {
   static constexpr int THREADS = 1024;

@@ -12,6 +12,7 @@ enum GridClass {
   G_TILE,      // interface-list rebuild: one tile of LTILE cells per block
   G_ONE,       // single-block kernels (one per domain)
   G_CELL,      // labelling kernels
+  G_EXCOUNT,   // excess mass (G_SMALL blocks) beside the tile counts (G_TILE)
   G_COUNT
 };
 
