@@ -280,6 +280,7 @@ LaunchCfg make_cfg(const fslbm_params &p, int bulk_threads = 256, int list_cells
   cfg.blocks[G_ONE] = 1;
   cfg.blocks[G_CELL] = clampb(4096, 1024);
   cfg.blocks[G_EXCOUNT] = cfg.blocks[G_SMALL] + cfg.blocks[G_TILE];
+  cfg.blocks[G_SCANCELL] = 1 + cfg.blocks[G_CELL];
   cfg.with_mass = 1;
   return cfg;
 }

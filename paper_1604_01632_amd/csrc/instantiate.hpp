@@ -43,12 +43,11 @@ static void phase_kernels(int ph, bool with_mass, int bulk_threads, L &&launch) 
       launch.template go<K_excess_count<P>>(G_EXCOUNT);
       break;
     case PH_GATHER:
-      launch.template go<K_list_scan>(G_ONE);
+      launch.template go<K_scan_label_init>(G_SCANCELL);
       launch.template go<K_list_fill>(G_TILE);
       launch.template go<K_gather<P>>(G_LIST);
       break;
     case PH_LABEL:
-      launch.template go<K_label_init>(G_CELL);
       launch.template go<K_label_union>(G_CELL);
       launch.template go<K_label_roots>(G_CELL);
       launch.template go<K_label_assign>(G_ONE);

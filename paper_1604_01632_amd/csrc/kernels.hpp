@@ -12,10 +12,14 @@
 //                 cells appended to a list (each once)
 //   k_conv_init   initial values of the new interface cells
 //   k_excess      excess mass of converted cells, bucket, topology trigger
+//                 (in one launch with the tile counts of the next
+//                 interface list)
+//   k_list_*      next interface list in cell order: count, scan (in one
+//                 launch with the labelled set of k_label_init), fill
 //   k_gather      interface cells of t+1 pull excess mass; fill levels;
-//                 per-bubble volume sums (Sec. 2.3); next interface list
+//                 per-bubble volume sums (Sec. 2.3)
 //   k_label_*     per-bubble volumes, bucket share and total mass (at the
-//                 start of k_label_init, every step); union-find labelling
+//                 start of k_label_union, every step); union-find labelling
 //                 of the gas region and the merge / split rules
 //                 (Sec. 2.3.1, 2.3.2) - the labelling returns at once
 //                 unless the trigger fired
@@ -1621,32 +1625,37 @@ struct K_excess_count {
 
 // Single block: exclusive scan of the tile counts.
 struct K_list_scan {
-  static constexpr int THREADS = 1024;
+  static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
-  __shared__ int sums[1024];
+  __shared__ int wtot[THREADS / 64];
   const int ntiles = (int)((d.N + LTILE - 1) / LTILE);
-  const int per = (ntiles + (int)blockDim.x - 1) / (int)blockDim.x;
-  const int lo = threadIdx.x * per;
+  const int per = (ntiles + THREADS - 1) / THREADS;
+  const int lo = (int)threadIdx.x * per;
   int t = 0;
   for (int k = lo; k < lo + per && k < ntiles; ++k) t += d.tilecount[k];
-  sums[threadIdx.x] = t;
-  __syncthreads();
-  // Hillis-Steele inclusive scan of the per-thread totals
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    const int v = threadIdx.x >= (unsigned)off ? sums[threadIdx.x - off] : 0;
-    __syncthreads();
-    sums[threadIdx.x] += v;
-    __syncthreads();
+  // inclusive scan of the per-thread totals: in the wave by shuffles, then
+  // over the wave totals
+  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+  int incl = t;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
   }
-  int run = sums[threadIdx.x] - t;
+  if (lane == 63) wtot[w] = incl;
+  __syncthreads();
+  int run = incl - t, total = 0;
+  for (int k = 0; k < THREADS / 64; ++k) {
+    if (k < w) run += wtot[k];
+    total += wtot[k];
+  }
   for (int k = lo; k < lo + per && k < ntiles; ++k) {
     const int c = d.tilecount[k];
     d.tileoff[k] = run;
     run += c;
   }
-  if (threadIdx.x == blockDim.x - 1) {
+  if (threadIdx.x == 0) {
     // beyond the capacity the list is cut (an error the host reports)
-    const int total = sums[threadIdx.x];
     if (total > d.icap) atomicOr(&d.sc->err, ERR_ILIST);
     d.sc->n_il_dst = total < d.icap ? total : d.icap;
   }
@@ -1692,8 +1701,8 @@ struct K_list_fill {
 
 // Per-bubble volume V = (gas + inlet cells) + sum over interface cells of
 // (1 - phi), exactly rounded (SUB lanes per bubble slot over the whole
-// grid); orphan bucket and total mass (block 0).  Runs at the start of the
-// first labelling kernel, every step.
+// grid); orphan bucket and total mass (block 0).  Runs after the gather
+// pass, at the start of the union pass, every step.
 __device__ __forceinline__ void bubble_volumes(const Dev &d, Blk bk) {
   __shared__ long long red[4][2];
   // one lane per (slot, sub-slot): the SUB lanes of a slot are
@@ -1873,7 +1882,6 @@ struct K_label_init {
   // the lanes before it in its wave hold (own entries only: no barrier)
   __shared__ uint32_t gbits[GROUP][THREADS];
   __shared__ int gpre[GROUP][THREADS];
-  bubble_volumes(d, bk);
   const int run = d.sc->label_run;
   if (!run) return;
   const bool all = run >= 2;
@@ -2036,6 +2044,20 @@ struct K_label_init {
 }
 };
 
+// The scan of the interface list's tile counts (block 0) and the labelled
+// set (the other blocks) in one launch: the set needs only the types and
+// slots of t+1 and the trigger's marks, all final once the excess pass is
+// done, and neither part reads what the other writes.
+struct K_scan_label_init {
+  static constexpr int THREADS = 256;
+  static_assert(K_list_scan::THREADS == THREADS && K_label_init::THREADS == THREADS,
+                "one block size for both parts");
+  static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
+  if (bk.id == 0) K_list_scan::run(d, Blk{0, 1});
+  else K_label_init::run(d, Blk{bk.id - 1, bk.n - 1});
+}
+};
+
 // Every edge of the set (one direction of every opposite pair).
 // Consecutive set cells usually share their label (one x-run) and so do
 // their neighbours in a direction: a lane whose (label, neighbour label)
@@ -2045,6 +2067,7 @@ struct K_label_init {
 struct K_label_union {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
+  bubble_volumes(d, bk);
   if (!d.sc->label_run) return;
   const int n = d.sc->n_lab;
   const int lane = (int)threadIdx.x & 63;

@@ -13,6 +13,7 @@ enum GridClass {
   G_ONE,       // single-block kernels (one per domain)
   G_CELL,      // labelling kernels
   G_EXCOUNT,   // excess mass (G_SMALL blocks) beside the tile counts (G_TILE)
+  G_SCANCELL,  // the tile-count scan (one block) beside the labelling init (G_CELL)
   G_COUNT
 };
 
