@@ -281,6 +281,8 @@ LaunchCfg make_cfg(const fslbm_params &p, int bulk_threads = 256, int list_cells
   cfg.blocks[G_CELL] = clampb(4096, 1024);
   cfg.blocks[G_EXCOUNT] = cfg.blocks[G_SMALL] + cfg.blocks[G_TILE];
   cfg.blocks[G_SCANCELL] = 1 + cfg.blocks[G_CELL];
+  cfg.blocks[G_TILECELL] = cfg.blocks[G_TILE] + cfg.blocks[G_CELL];
+  cfg.blocks[G_VOLCELL] = volume_blocks(p.max_bubbles, 256) + cfg.blocks[G_CELL];
   cfg.with_mass = 1;
   return cfg;
 }

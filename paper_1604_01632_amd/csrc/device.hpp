@@ -30,6 +30,12 @@ constexpr uint8_t GATHER = 0x80;
 // slots (picked by block index) to avoid serialising on one address; the
 // slots are integers, so the final sum is independent of order.
 constexpr int SUB = 16;
+// Blocks of `threads` lanes for the per-bubble volume reduction: one lane
+// per bubble slot and sub-slot, at most 1024 blocks (grid-stride beyond).
+__host__ __device__ constexpr int volume_blocks(int max_bubbles, int threads) {
+  const long long n = ((long long)max_bubbles * SUB + threads - 1) / threads;
+  return (int)(n < 1024 ? n : 1024);
+}
 constexpr int SUB_MASS = 256;
 
 // Fixed-point scale of the two-word integer accumulator of the total mass

@@ -44,12 +44,11 @@ static void phase_kernels(int ph, bool with_mass, int bulk_threads, L &&launch) 
       break;
     case PH_GATHER:
       launch.template go<K_scan_label_init>(G_SCANCELL);
-      launch.template go<K_list_fill>(G_TILE);
+      launch.template go<K_fill_label_union>(G_TILECELL);
       launch.template go<K_gather<P>>(G_LIST);
       break;
     case PH_LABEL:
-      launch.template go<K_label_union>(G_CELL);
-      launch.template go<K_label_roots>(G_CELL);
+      launch.template go<K_volume_label_roots>(G_VOLCELL);
       launch.template go<K_label_assign>(G_ONE);
       launch.template go<K_label_accumulate<P>>(G_CELL);
       break;

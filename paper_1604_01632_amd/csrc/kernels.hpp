@@ -15,11 +15,12 @@
 //                 (in one launch with the tile counts of the next
 //                 interface list)
 //   k_list_*      next interface list in cell order: count, scan (in one
-//                 launch with the labelled set of k_label_init), fill
+//                 launch with the labelled set of k_label_init), fill (in
+//                 one launch with the unions of k_label_union)
 //   k_gather      interface cells of t+1 pull excess mass; fill levels;
 //                 per-bubble volume sums (Sec. 2.3)
-//   k_label_*     per-bubble volumes, bucket share and total mass (at the
-//                 start of k_label_union, every step); union-find labelling
+//   k_label_*     per-bubble volumes, bucket share and total mass (in one
+//                 launch with k_label_roots, every step); union-find labelling
 //                 of the gas region and the merge / split rules
 //                 (Sec. 2.3.1, 2.3.2) - the labelling returns at once
 //                 unless the trigger fired
@@ -1702,7 +1703,7 @@ struct K_list_fill {
 // Per-bubble volume V = (gas + inlet cells) + sum over interface cells of
 // (1 - phi), exactly rounded (SUB lanes per bubble slot over the whole
 // grid); orphan bucket and total mass (block 0).  Runs after the gather
-// pass, at the start of the union pass, every step.
+// pass, in the blocks before those of the roots pass, every step.
 __device__ __forceinline__ void bubble_volumes(const Dev &d, Blk bk) {
   __shared__ long long red[4][2];
   // one lane per (slot, sub-slot): the SUB lanes of a slot are
@@ -2067,7 +2068,6 @@ struct K_scan_label_init {
 struct K_label_union {
   static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
-  bubble_volumes(d, bk);
   if (!d.sc->label_run) return;
   const int n = d.sc->n_lab;
   const int lane = (int)threadIdx.x & 63;
@@ -2120,6 +2120,22 @@ struct K_label_union {
 }
 };
 
+// The fill of the interface list of t+1 (one block per tile) and the
+// unions of the labelled set (the blocks after them) in one launch: the
+// unions read and write only the labels, which neither the fill nor the
+// gather pass after it touch, and the fill reads only the types of t+1
+// and the scanned tile offsets.
+struct K_fill_label_union {
+  static constexpr int THREADS = 256;
+  static_assert(K_list_fill::THREADS == THREADS && K_label_union::THREADS == THREADS,
+                "one block size for both parts");
+  static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
+  const int ntiles = (int)((d.N + LTILE - 1) / LTILE);
+  if (bk.id < ntiles) K_list_fill::run(d, Blk{bk.id, ntiles});
+  else K_label_union::run(d, Blk{bk.id - ntiles, bk.n - ntiles});
+}
+};
+
 // Final roots (the trees no longer change: plain loads).  Every root
 // registers itself with its bubble; an edge between cells of two bubbles
 // marks the component as mixed and registers it with both bubbles, so that
@@ -2168,6 +2184,20 @@ struct K_label_roots {
       atomicMax(&d.b_rmax[sj], r);
     }
   }
+}
+};
+
+// The per-bubble volumes (the first blocks: one lane per bubble slot and
+// sub-slot) and the roots pass (the blocks after them) in one launch: the
+// roots pass reads none of what the volume reduction writes, and the
+// assign pass after both needs the volumes.
+struct K_volume_label_roots {
+  static constexpr int THREADS = 256;
+  static_assert(K_label_roots::THREADS == THREADS, "one block size for both parts");
+  static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
+  const int nv = volume_blocks(d.max_bubbles, THREADS);
+  if (bk.id < nv) bubble_volumes(d, Blk{bk.id, nv});
+  else K_label_roots::run(d, Blk{bk.id - nv, bk.n - nv});
 }
 };
 
