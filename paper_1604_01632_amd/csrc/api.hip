@@ -55,7 +55,7 @@ bool launchers_for(int precision, Launchers &L) {
 enum Arr {
   A_F0, A_F1, A_FLAG0, A_FLAG1, A_PHI0, A_PHI1, A_MASS, A_RHOI, A_EXCESS, A_BSLOT, A_LAB,
   A_AUX0, A_AUX2, A_BID, A_BFLAGS, A_BLIVE, A_BRMIN, A_BRMAX, A_BKEPT, A_BAFFECT, A_NEWROOTS,
-  A_NEWSLOT, A_BVSTAR, A_BVOL, A_BP, A_BRATIO, A_BNGAS, A_BNIFACE, A_BVACC, A_CACC,
+  A_NEWSLOT, A_BVSTAR, A_BVOL, A_BP, A_BNGAS, A_BNIFACE, A_BVACC, A_CACC,
   A_SCALARS, A_MASSACC, A_BUCKETACC, A_ILIST0, A_ILIST1, A_CLIST, A_NLIST, A_MARK, A_GASV, A_NMASK, A_NRM, A_TILECOUNT, A_TILEOFF,
   A_FIF0, A_FIF1, A_NFLAG, A_ISLOT0, A_ISLOT1, A_COUNT
 };
@@ -85,7 +85,7 @@ Layout make_layout(const fslbm_params &p, const Launchers &L) {
   sz[A_BSLOT] = sz[A_LAB] = sz[A_AUX0] = sz[A_AUX2] = N * 4;
   sz[A_BID] = sz[A_BFLAGS] = sz[A_BLIVE] = sz[A_BRMIN] = sz[A_BRMAX] = sz[A_BKEPT] = sz[A_BAFFECT] =
       sz[A_NEWROOTS] = sz[A_NEWSLOT] = B * 4;
-  sz[A_BVSTAR] = sz[A_BVOL] = sz[A_BP] = sz[A_BRATIO] = sz[A_BNGAS] = sz[A_BNIFACE] = B * 8;
+  sz[A_BVSTAR] = sz[A_BVOL] = sz[A_BP] = sz[A_BNGAS] = sz[A_BNIFACE] = B * 8;
   sz[A_BVACC] = B * SUB * VACC * 8;
   sz[A_CACC] = B * SUB * NACC * 8;
   sz[A_SCALARS] = sizeof(Scalars);
@@ -226,7 +226,6 @@ void build_devs(Ctx &c) {
   d.b_vstar = at<double>(ws, lay, A_BVSTAR);
   d.b_vol = at<double>(ws, lay, A_BVOL);
   d.b_p = at<double>(ws, lay, A_BP);
-  d.b_ratio = at<double>(ws, lay, A_BRATIO);
   d.b_ngas = at<long long>(ws, lay, A_BNGAS);
   d.b_niface = at<long long>(ws, lay, A_BNIFACE);
   d.b_vacc = at<unsigned long long>(ws, lay, A_BVACC);
@@ -278,11 +277,12 @@ LaunchCfg make_cfg(const fslbm_params &p, int bulk_threads = 256, int list_cells
   cfg.blocks[G_SMALL] = clampb(4096, 256);
   cfg.blocks[G_TILE] = (int)((N + 4095) / 4096);
   cfg.blocks[G_ONE] = 1;
-  cfg.blocks[G_CELL] = clampb(4096, 1024);
+  cfg.blocks[G_CELL] = cell_blocks(N);
   cfg.blocks[G_EXCOUNT] = cfg.blocks[G_SMALL] + cfg.blocks[G_TILE];
   cfg.blocks[G_SCANCELL] = 1 + cfg.blocks[G_CELL];
   cfg.blocks[G_TILECELL] = cfg.blocks[G_TILE] + cfg.blocks[G_CELL];
-  cfg.blocks[G_VOLCELL] = volume_blocks(p.max_bubbles, 256) + cfg.blocks[G_CELL];
+  cfg.blocks[G_LISTCELL] = cfg.blocks[G_LIST] + cfg.blocks[G_CELL];
+  cfg.blocks[G_ONEVOL] = 1 + volume_blocks(p.max_bubbles, 256);
   cfg.with_mass = 1;
   return cfg;
 }

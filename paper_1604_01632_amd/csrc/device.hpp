@@ -36,6 +36,12 @@ __host__ __device__ constexpr int volume_blocks(int max_bubbles, int threads) {
   const long long n = ((long long)max_bubbles * SUB + threads - 1) / threads;
   return (int)(n < 1024 ? n : 1024);
 }
+// Blocks of the labelling kernels: one per 4096 cells, at most 1024 (they
+// walk the labelled set with grid strides).
+__host__ __device__ constexpr int cell_blocks(long long n_cells) {
+  const long long b = (n_cells + 4095) / 4096;
+  return (int)(b < 1 ? 1 : (b < 1024 ? b : 1024));
+}
 constexpr int SUB_MASS = 256;
 
 // Fixed-point scale of the two-word integer accumulator of the total mass
@@ -130,7 +136,7 @@ struct Dev {
   int32_t *lab, *aux0, *aux2;
   // bubble table, indexed by slot
   int32_t *b_id, *b_flags, *b_live;
-  double *b_vstar, *b_vol, *b_p, *b_ratio;
+  double *b_vstar, *b_vol, *b_p;
   long long *b_ngas, *b_niface;
   int32_t *b_rmin, *b_rmax, *b_kept;
   int32_t *b_affect;            // marked by the topology trigger this step

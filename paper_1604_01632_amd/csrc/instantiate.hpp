@@ -45,11 +45,10 @@ static void phase_kernels(int ph, bool with_mass, int bulk_threads, L &&launch) 
     case PH_GATHER:
       launch.template go<K_scan_label_init>(G_SCANCELL);
       launch.template go<K_fill_label_union>(G_TILECELL);
-      launch.template go<K_gather<P>>(G_LIST);
+      launch.template go<K_gather_label_roots<P>>(G_LISTCELL);
       break;
     case PH_LABEL:
-      launch.template go<K_volume_label_roots>(G_VOLCELL);
-      launch.template go<K_label_assign>(G_ONE);
+      launch.template go<K_assign_volumes>(G_ONEVOL);
       launch.template go<K_label_accumulate<P>>(G_CELL);
       break;
     case PH_BUBBLES:

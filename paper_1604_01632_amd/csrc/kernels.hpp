@@ -18,9 +18,10 @@
 //                 launch with the labelled set of k_label_init), fill (in
 //                 one launch with the unions of k_label_union)
 //   k_gather      interface cells of t+1 pull excess mass; fill levels;
-//                 per-bubble volume sums (Sec. 2.3)
+//                 per-bubble volume sums (Sec. 2.3) (in one launch with the
+//                 roots of k_label_roots)
 //   k_label_*     per-bubble volumes, bucket share and total mass (in one
-//                 launch with k_label_roots, every step); union-find labelling
+//                 launch with k_label_assign, every step); union-find labelling
 //                 of the gas region and the merge / split rules
 //                 (Sec. 2.3.1, 2.3.2) - the labelling returns at once
 //                 unless the trigger fired
@@ -1703,7 +1704,7 @@ struct K_list_fill {
 // Per-bubble volume V = (gas + inlet cells) + sum over interface cells of
 // (1 - phi), exactly rounded (SUB lanes per bubble slot over the whole
 // grid); orphan bucket and total mass (block 0).  Runs after the gather
-// pass, in the blocks before those of the roots pass, every step.
+// pass, in the blocks after the assign pass's, every step.
 __device__ __forceinline__ void bubble_volumes(const Dev &d, Blk bk) {
   __shared__ long long red[4][2];
   // one lane per (slot, sub-slot): the SUB lanes of a slot are
@@ -2187,26 +2188,12 @@ struct K_label_roots {
 }
 };
 
-// The per-bubble volumes (the first blocks: one lane per bubble slot and
-// sub-slot) and the roots pass (the blocks after them) in one launch: the
-// roots pass reads none of what the volume reduction writes, and the
-// assign pass after both needs the volumes.
-struct K_volume_label_roots {
-  static constexpr int THREADS = 256;
-  static_assert(K_label_roots::THREADS == THREADS, "one block size for both parts");
-  static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
-  const int nv = volume_blocks(d.max_bubbles, THREADS);
-  if (bk.id < nv) bubble_volumes(d, Blk{bk.id, nv});
-  else K_label_roots::run(d, Blk{bk.id - nv, bk.n - nv});
-}
-};
-
 // Single block: decide, per listed root, whether its component keeps its
 // bubble; order the new components by their smallest cell index, give each
 // the next fresh ID and a free slot, and fix the V* ratio of every old
 // bubble.
 struct K_label_assign {
-  static constexpr int THREADS = 1024;
+  static constexpr int THREADS = 256;
   static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
   if (!d.sc->label_run) return;
   Scalars *sc = d.sc;
@@ -2248,13 +2235,6 @@ struct K_label_assign {
   for (int k = threadIdx.x; k < nnew; k += blockDim.x) d.newroots[k] = d.newslot[k];
   __syncthreads();
   for (int k = threadIdx.x; k < nnew; k += blockDim.x) d.aux0[d.newroots[k]] = k;
-  // V* per unit gas volume of every old bubble (per cell if V <= 0)
-  for (int s = threadIdx.x; s < B; s += blockDim.x) {
-    if (!d.b_live[s]) continue;
-    const double v = d.b_vol[s];
-    const long long nc = d.b_ngas[s] + d.b_niface[s];
-    d.b_ratio[s] = v > 0.0 ? d.b_vstar[s] / v : -(d.b_vstar[s] / (double)(nc > 0 ? nc : 1));
-  }
   __syncthreads();
   // the first nnew free slots in increasing order: a block-wide prefix
   // count of the free slots, chunk by chunk
@@ -2287,6 +2267,35 @@ struct K_label_assign {
     if (k < nnew) sc->err |= ERR_CAPACITY;
     sc->nfree = k;
   }
+}
+};
+
+// The gather pass (its G_LIST blocks) and the roots pass (the blocks after
+// them) in one launch: the roots pass reads the labels, slots and types of
+// t+1, which the gather pass does not write, and writes only labels, root
+// ranges and the root list, which the gather pass does not read.
+template <class P>
+struct K_gather_label_roots {
+  static constexpr int THREADS = 256;
+  static_assert(K_gather<P>::THREADS == THREADS && K_label_roots::THREADS == THREADS,
+                "one block size for both parts");
+  static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
+  const int nc = cell_blocks(d.N), ng = bk.n - nc;
+  if (bk.id < ng) K_gather<P>::run(d, Blk{bk.id, ng});
+  else K_label_roots::run(d, Blk{bk.id - ng, nc});
+}
+};
+
+// The assign pass (block 0) and the per-bubble volume reduction (the blocks
+// after it: one lane per bubble slot and sub-slot) in one launch: the
+// volumes need the gather pass, and the accumulate pass after both reads
+// them; the assign pass reads none of what the reduction writes.
+struct K_assign_volumes {
+  static constexpr int THREADS = 256;
+  static_assert(K_label_assign::THREADS == THREADS, "one block size for both parts");
+  static __device__ __forceinline__ void run(const Dev &d, Blk bk) {
+  if (bk.id == 0) K_label_assign::run(d, Blk{0, 1});
+  else bubble_volumes(d, Blk{bk.id - 1, bk.n - 1});
 }
 };
 
@@ -2323,12 +2332,14 @@ struct K_label_accumulate {
       const R ph = ((const R *)d.phi_dst)[i];
       const int sl = d.bslot[i];
       const int a2 = d.aux2[r], a0 = d.aux0[r];
-      const double rt = d.b_ratio[sl];
+      const double bv = d.b_vol[sl], bvs = d.b_vstar[sl];
+      const long long nc = d.b_ngas[sl] + d.b_niface[sl];
       const int bfl = d.b_flags[sl];
       if (ok && (a2 & 2)) {
         key = a0;
         const double w = t == T_IFACE ? 1.0 - (double)ph : 1.0;
-        const double ratio = rt;
+        // V* per unit gas volume of the old bubble (per cell if V <= 0)
+        const double ratio = bv > 0.0 ? bvs / bv : -(bvs / (double)(nc > 0 ? nc : 1));
         const double ws = ratio >= 0.0 ? ratio * w : -ratio;
         const ExTerm tw = ex_split(w), ts = ex_split(ws);
 #pragma unroll

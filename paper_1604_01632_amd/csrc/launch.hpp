@@ -15,8 +15,9 @@ enum GridClass {
   G_EXCOUNT,   // excess mass (G_SMALL blocks) beside the tile counts (G_TILE)
   G_SCANCELL,  // the tile-count scan (one block) beside the labelling init (G_CELL)
   G_TILECELL,  // the list fill (G_TILE) beside the labelling unions (G_CELL)
-  G_VOLCELL,   // the bubble volumes (one lane per slot and sub-slot) beside
-               // the roots pass (G_CELL)
+  G_LISTCELL,  // the gather pass (G_LIST) beside the roots pass (G_CELL)
+  G_ONEVOL,    // the assign pass (one block) beside the bubble volumes (one
+               // lane per slot and sub-slot)
   G_COUNT
 };
 
