@@ -243,11 +243,15 @@ int fslbm_sync(void *handle);
 
 /* GPU time per phase of the sampled steps enqueued while timing was
  * enabled, measured with HIP events on the handle's stream (bulk = liquid-cell
- * stream-collide kernel, iface = geometry and interface kernels, gather =
- * interface-list rebuild and excess gather, label = per-bubble volume sums
- * (every step) and the labelling kernels, which return at once unless a
- * topology change is possible, bubbles = installing the new bubbles of a
- * labelling run and the pressure update). */
+ * stream-collide kernel, iface = geometry and interface kernels, convert =
+ * new cell types and new interface cells, excess = excess mass, topology
+ * trigger and the tile counts of the next interface list, gather = the rest
+ * of the list rebuild, the excess gather, and the labelled set, unions and
+ * roots of a labelling run (independent work that shares their launches),
+ * label = per-bubble volume sums (every step) and the rest of the labelling,
+ * bubbles = installing the new bubbles of a labelling run and the pressure
+ * update).  The labelling kernels return at once unless a topology change
+ * is possible. */
 typedef struct {
   double bulk_ms, iface_ms, convert_ms, excess_ms, gather_ms, label_ms, bubbles_ms;
   double step_ms;   /* sum of the above */
