@@ -282,7 +282,9 @@ LaunchCfg make_cfg(const fslbm_params &p, int bulk_threads = 256, int list_cells
   cfg.blocks[G_SCANCELL] = 1 + cfg.blocks[G_CELL];
   cfg.blocks[G_TILECELL] = cfg.blocks[G_TILE] + cfg.blocks[G_CELL];
   cfg.blocks[G_LISTCELL] = cfg.blocks[G_LIST] + cfg.blocks[G_CELL];
-  cfg.blocks[G_ONEVOL] = 1 + volume_blocks(p.max_bubbles, 256);
+  // the volume reduction walks the bubble slots with grid strides: a small
+  // domain of a batch gets no more blocks for it than for its labelling
+  cfg.blocks[G_ONEVOL] = 1 + std::min(volume_blocks(p.max_bubbles, 256), cell_blocks(N));
   cfg.with_mass = 1;
   return cfg;
 }

@@ -1,6 +1,8 @@
 // Kernel launch sequence of one step for one precision, for one domain or
 // for a batch of domains.  Included by one translation unit per precision.
 #pragma once
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -23,8 +25,16 @@ static void phase_kernels(int ph, bool with_mass, int bulk_threads, L &&launch) 
   switch (ph) {
     case PH_IFACE:
       launch.template go<K_geom<P>>(G_LIST);
-      if (with_mass) launch.template go<K_iface<P, true>>(G_LIST);
-      else launch.template go<K_iface<P, false>>(G_LIST);
+      // one domain appends its candidates per block, a batch per wave (a
+      // domain of a batch has a short list, and the block-wide append's
+      // barriers slow the batched kernel by 7 %)
+      if constexpr (std::remove_reference_t<L>::kBatch) {
+        if (with_mass) launch.template go<K_iface<P, true, false>>(G_LIST);
+        else launch.template go<K_iface<P, false, false>>(G_LIST);
+      } else {
+        if (with_mass) launch.template go<K_iface<P, true, true>>(G_LIST);
+        else launch.template go<K_iface<P, false, true>>(G_LIST);
+      }
       break;
     case PH_BULK:
       if (bulk_threads == 128) {
@@ -40,7 +50,15 @@ static void phase_kernels(int ph, bool with_mass, int bulk_threads, L &&launch) 
       launch.template go<K_conv_init<P>>(G_SMALL);
       break;
     case PH_EXCESS:
-      launch.template go<K_excess_count<P>>(G_EXCOUNT);
+      if constexpr (std::remove_reference_t<L>::kBatch) {
+        // many domains: the tile counts in a launch of their own (the
+        // excess pass's registers would hold the tens of thousands of
+        // count blocks of a batch to two waves per SIMD)
+        launch.template go<K_excess<P>>(G_SMALL);
+        launch.template go<K_list_count>(G_TILE);
+      } else {
+        launch.template go<K_excess_count<P>>(G_EXCOUNT);
+      }
       break;
     case PH_GATHER:
       launch.template go<K_scan_label_init>(G_SCANCELL);
@@ -60,6 +78,7 @@ static void phase_kernels(int ph, bool with_mass, int bulk_threads, L &&launch) 
 }
 
 struct OneLauncher {
+  static constexpr bool kBatch = false;
   const Dev &d;
   const LaunchCfg &c;
   hipStream_t s;
@@ -70,6 +89,7 @@ struct OneLauncher {
 };
 
 struct ManyLauncher {
+  static constexpr bool kBatch = true;
   const BatchCfg &b;
   hipStream_t s;
   template <class K>

@@ -1039,9 +1039,22 @@ __device__ __forceinline__ double iface_cell(const Dev &d, int x, int y, int z, 
   return (double)m_new;
 }
 
-// Appends the lanes with pred set to a list with one atomic for the whole
-// block (the appends of all blocks serialise on the one counter); returns
-// each such lane's slot, -1 for the others.  Every thread of the block must
+// Appends the lanes with pred set to a list; returns each such lane's slot,
+// -1 for the others.  Every lane of the wave must call it.
+__device__ __forceinline__ int wave_append(bool pred, int *counter) {
+  const unsigned long long m = __ballot(pred);
+  if (!m) return -1;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, (int)__popcll(m));
+  base = __shfl(base, leader, 64);
+  return pred ? base + (int)__popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
+
+// The same with one atomic for the whole block: the appends of all waves
+// serialise on the one counter, which costs more than the block's barriers
+// once thousands of waves append to it.  Every thread of the block must
 // call it.
 __device__ __forceinline__ int block_append(bool pred, int *counter) {
   __shared__ int bw[16];
@@ -1063,10 +1076,11 @@ __device__ __forceinline__ int block_append(bool pred, int *counter) {
 }
 
 // Interface cells of time t (list), one per thread; conversion candidates
-// are appended to the candidate list.  The list of a step is about one
-// round of resident waves, so the FP32/FP16 kernels are held to three waves
-// per SIMD (the FP64 one would spill).
-template <class P, bool WITH_MASS>
+// are appended to the candidate list, with one atomic per block
+// (BLOCK_APPEND) or per wave.  The list of a step is about one round of
+// resident waves, so the FP32/FP16 kernels are held to three waves per SIMD
+// (the FP64 one would spill).
+template <class P, bool WITH_MASS, bool BLOCK_APPEND>
 struct K_iface {
   static constexpr int THREADS = 256;
   static constexpr int MIN_WAVES = P::EXACT ? 1 : 3;
@@ -1089,7 +1103,8 @@ struct K_iface {
     }
     // at most one entry per cell and step (the counter is reset at the
     // end of the step); the bound only guards the list
-    const int pos = block_append(cand, &d.sc->n_cand);
+    const int pos = BLOCK_APPEND ? block_append(cand, &d.sc->n_cand)
+                                 : wave_append(cand, &d.sc->n_cand);
     if (cand) {
       if (pos < (int)d.N) d.clist[pos] = (int)i;
       else atomicOr(&d.sc->err, ERR_RANGE);
