@@ -354,7 +354,7 @@ int fslbm_batch_create(void *const *handles, int32_t n, const char *tuning_cache
  * `stream`, and each batch step is the plain launch of the step kernels on
  * it (no tuning: 256-thread stream-collide blocks, domains as given).  The
  * domains compute bit for bit what they compute alone or in any batch.
- * At most about 4000 domains (EINVAL beyond the array, with the sizes in
+ * At most about 3700 domains (EINVAL beyond the array, with the sizes in
  * the message).  All such batches on one GPU share the one array: creating
  * one overwrites the tables of the one before, which must not be stepped
  * again; calls that overlap on one GPU race.  Use fslbm_batch_step and
