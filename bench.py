@@ -144,6 +144,20 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_p1_256cubed_fp32_hbm_traff
 CSRC = os.path.join(ROOT, "paper_1604_01632_amd", "csrc")
 
 
+# What each timed phase of one domain's step holds (passes that touch
+# disjoint data share a launch, so a phase can hold part of another's work).
+PHASE_PASSES = {
+    "bulk_ms": "stream-collide",
+    "iface_ms": "geometry, interface update",
+    "convert_ms": "new cell types, new interface cells",
+    "excess_ms": "excess mass and topology trigger; tile counts of the next interface list",
+    "gather_ms": "tile-count scan and labelled set; list fill and unions; excess gather, "
+                 "volume sums and roots",
+    "label_ms": "assign and per-bubble volumes; new components' sums",
+    "bubbles_ms": "install, injection, pressure",
+}
+
+
 def kernel_source_hash() -> str:
     """SHA-256 over the HIP sources of the library (sorted by name): the
     recorded HBM traffic is valid only for the kernels it was measured on."""
@@ -763,6 +777,7 @@ def main() -> int:
             "whole_step_bytes_per_fluid_cell": b_alg,
             "bulk_sampled_steps": int(T["steps"]),
             "phase_us": phases,
+            "phase_passes": PHASE_PASSES if phases else None,
             "split_triggers": triggers,
             "achievable_copy": copy,
         },
